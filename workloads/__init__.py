@@ -1,0 +1,26 @@
+"""Seeded synthetic workloads shared by the FP64 oracle and the HIP path.
+
+This package only builds inputs (grids, bathymetry, Coriolis fields, initial
+states, forcing snapshots).  It holds none of the finite-volume scheme's
+arithmetic, so both implementations can consume the very same FP32 arrays.
+"""
+
+from .configs import (  # noqa: F401
+    BC_NESTED,
+    BC_PERIODIC,
+    BC_WALL,
+    FRIC_LINEAR,
+    FRIC_MANNING,
+    FRIC_NONE,
+    FRIC_QUADRATIC,
+    Workload,
+    config1,
+    config2,
+    config3,
+    config4_member,
+    config4_sizes,
+    config5_requests,
+    convergence_case,
+    perimeter_len,
+    random_small,
+)

@@ -1,0 +1,170 @@
+/*
+ * swe.h -- C ABI of the MI355X (gfx950) implementation of the eta-based,
+ * well-balanced central-upwind finite-volume scheme for the rotational
+ * shallow-water equations of Brodtkorb & Holm, "Real-World Oceanographic
+ * Simulations on the GPU using a Two-Dimensional Finite-Volume Scheme"
+ * (arXiv 1912.02457).
+ *
+ * Conventions used by every entry point:
+ *   - Cell fields are row-major [ny][nx] float32, x fastest; corner depths
+ *     are [ny+1][nx+1] float32 (equilibrium depth H, metres, positive
+ *     downwards, at the cell intersections: the piecewise bilinear bathymetry
+ *     of the section "Mathematical formulation", Figure 1b).
+ *   - The land mask is an optional uint8 [ny][nx] array (nonzero = land).
+ *   - Units are SI.  Times are float64 seconds.
+ *   - Host arrays passed in are read during the call and copied; the library
+ *     never keeps a host pointer.  Device memory comes from ONE caller-owned
+ *     workspace (size from swe_workspace_bytes) that stays borrowed for the
+ *     lifetime of the domain handle; the library allocates no device memory
+ *     of its own for a domain.
+ *   - All GPU work of a domain is issued on the HIP stream given at init
+ *     (NULL = the null stream).  Calls marked "asynchronous" only enqueue.
+ *   - Every function returns SWE_OK (0) or a negative error code; the message
+ *     of the last error on the calling thread is in swe_last_error().  No C++
+ *     exception crosses this interface.
+ */
+#ifndef SWE_H
+#define SWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define SWE_OK 0
+#define SWE_E_ARG (-1)      /* invalid size, parameter, pointer or non-finite input */
+#define SWE_E_NOMEM (-2)    /* caller workspace too small */
+#define SWE_E_HIP (-3)      /* HIP runtime error; message in swe_last_error() */
+#define SWE_E_UNSTABLE (-4) /* a step produced a non-finite state (flag raised on the device) */
+#define SWE_E_STATE (-5)    /* call out of order (e.g. nested sides without boundary data) */
+
+/* boundary kinds, per side in the order West, East, South, North */
+#define SWE_BC_WALL 0     /* reflective wall, section "Global wall boundary conditions" */
+#define SWE_BC_PERIODIC 1 /* periodic; must be set on both sides of an axis */
+#define SWE_BC_NESTED 2   /* external state + flow relaxation, section "Nesting the model" */
+
+/* bed shear stress laws, section "Wind forcing and bed friction source terms";
+ * the source is -S(Q) (hu, hv) with h* the desingularised depth of eq. desing_ours */
+#define SWE_FRICTION_NONE 0
+#define SWE_FRICTION_LINEAR 1    /* S = r / h*           (r in m/s)            */
+#define SWE_FRICTION_QUADRATIC 2 /* S = r |u| / h*^2     (eq. swe as printed)  */
+#define SWE_FRICTION_MANNING 3   /* S = g n^2 |u| / h*^(4/3)                   */
+
+/* forcing kinds for swe_set_forcing */
+#define SWE_FORCING_WIND_STRESS 0 /* uniform wind stress (N/m^2), snapshots in time */
+#define SWE_FORCING_BOUNDARY 1    /* external (eta, hu, hv) along the perimeter      */
+
+typedef struct swe_params {
+    int32_t nx, ny;          /* cells, each >= 2 */
+    double dx, dy;           /* cell size (m) */
+    double g;                /* gravity (m/s^2), e.g. 9.81 */
+    double courant;          /* C in dt = C * 1/4 * min(dx/(|u|+c), dy/(|v|+c)), eq. cfl; 0 < C <= 1 */
+    double theta;            /* generalized-minmod parameter in [1, 2] */
+    double kappa;            /* desingularisation / dry tolerance (m), eq. desing_ours; > 0 */
+    int32_t bc[4];           /* SWE_BC_* for W, E, S, N */
+    int32_t friction;        /* SWE_FRICTION_* */
+    double friction_coeff;   /* r (m/s), r (-), or Manning n (s m^-1/3) */
+    double rho_w;            /* sea-water density (kg/m^3) dividing the wind stress, e.g. 1025 */
+    int32_t frs_width;       /* relaxation zone width W in cells (1..32), eq. frs */
+    double frs_d0;           /* relaxation length d0 in cells, eq. frs; > 0 */
+    int32_t north_projection;/* 0: Coriolis as f (hv, -hu); 1: evaluate the north-vector
+                                projection of the section "Coriolis force" literally
+                                (reads the north angle every stage) */
+} swe_params;
+
+typedef struct swe_domain swe_domain;
+
+/* Bytes of device workspace that swe_init_domain needs for these parameters
+ * (state double buffer, bathymetry, Coriolis field, forcing tables, control
+ * block).  max_bnd_times / max_wind_times bound the forcing snapshots that
+ * swe_set_forcing may later hold.  Returns SWE_E_ARG for invalid parameters. */
+int swe_workspace_bytes(const swe_params *p, int32_t max_wind_times, int32_t max_bnd_times,
+                        size_t *bytes);
+
+/* Create a domain: validate p, upload the problem statement of the sections
+ * "Mathematical formulation" and "Efficient simulation of real-world ocean
+ * currents" -- corner depths Hc [ny+1][nx+1], optional land mask [ny][nx],
+ * Coriolis parameter f [ny][nx] (section "Coriolis force"), north angle theta
+ * [ny][nx] (radians between the grid y-axis and north, may be NULL = 0) and
+ * the initial state eta, hu, hv [ny][nx] -- into the caller's device
+ * workspace (device pointer, 256-byte aligned, `bytes` long, borrowed until
+ * swe_destroy), and compute the first CFL time step on the device.  Host
+ * arrays are copied.  Launches go on `hip_stream` (a hipStream_t, may be
+ * NULL); the call synchronises that stream before returning.
+ * Errors: SWE_E_ARG (sizes < 2, non-finite inputs, bad parameters, periodic
+ * on one side only, periodic seam depths that differ), SWE_E_NOMEM, SWE_E_HIP. */
+int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
+                    int32_t max_wind_times, int32_t max_bnd_times, const float *Hc,
+                    const uint8_t *land, const float *f, const float *theta, const float *eta,
+                    const float *hu, const float *hv, swe_domain **out);
+
+/* Forcing snapshots, linearly interpolated in time in float64 on the device
+ * (eq. windstress_interpol; nesting data as in the section "Nesting the
+ * model"), clamped outside [times[0], times[n-1]].
+ *   SWE_FORCING_WIND_STRESS: data = n_times x 2 (tau_x, tau_y) in N/m^2; the
+ *     momentum source is tau / rho_w (uniform in space).
+ *   SWE_FORCING_BOUNDARY: data = n_times x 3 x (2 ny + 2 nx) for (eta, hu, hv)
+ *     along the West strip (by row), East strip, South strip (by column) and
+ *     North strip.  Ghost cells of nested sides take these values and the
+ *     relaxation zone is nudged toward them.
+ * times must increase strictly.  Host arrays, copied; synchronises the stream.
+ * Errors: SWE_E_ARG (n_times < 1 or above the workspace bound, non-finite
+ * data, unknown kind), SWE_E_HIP. */
+int swe_set_forcing(swe_domain *d, int32_t kind, int32_t n_times, const double *times,
+                    const float *data);
+
+/* Advance n_steps SSP-RK2 steps (eq. rk2_semiimp with the spatial operator of
+ * eq. sw_semidiscrete), each with the dt of eq. cfl computed on the device
+ * from the state at the start of the step.  Asynchronous: no host
+ * synchronisation.  Uses a captured HIP graph of the two stage kernels once
+ * the step count repeats.  Errors: SWE_E_ARG (n_steps < 0), SWE_E_STATE
+ * (nested side without boundary data), SWE_E_HIP. */
+int swe_step(swe_domain *d, int32_t n_steps);
+
+/* Like swe_step but with the time step of step k given by dts[k] (host
+ * array of n_steps float64 values > 0): replays a known dt sequence.
+ * Asynchronous. */
+int swe_step_dt(swe_domain *d, int32_t n_steps, const double *dts);
+
+/* Advance until t == t_end: the last step is shortened on the device so that
+ * t lands on t_end exactly.  Synchronises; *steps_taken (may be NULL) gets
+ * the number of steps.  Returns SWE_E_UNSTABLE if the state became
+ * non-finite. */
+int swe_run_until(swe_domain *d, double t_end, int64_t *steps_taken);
+
+/* Copy the state into caller buffers (each [ny][nx] float32; host or device
+ * pointers, any may be NULL) and report time t and the dt of the next step.
+ * Synchronises.  Returns SWE_E_UNSTABLE if the device flag is set. */
+int swe_read_state(swe_domain *d, float *eta, float *hu, float *hv, double *t, double *dt_next);
+
+/* Replace the state (host arrays [ny][nx]) and the time; recomputes the
+ * next dt.  For checkpoint/resume.  Synchronises. */
+int swe_set_state(swe_domain *d, const float *eta, const float *hu, const float *hv, double t);
+
+/* Float64 reductions over non-land cells: mass = sum (eta + Hbar) dx dy and
+ * energy = sum (|hu|^2 / (2 h*) + g eta^2 / 2) dx dy, Hbar the mean of the
+ * four corner depths.  Deterministic order.  Synchronises. */
+int swe_diagnostics(swe_domain *d, double *mass, double *energy);
+
+/* SWE_OK, or SWE_E_UNSTABLE once a step produced a non-finite value.
+ * Synchronises. */
+int swe_status(swe_domain *d);
+
+/* Average device time per launch of each stage kernel (milliseconds) over
+ * the launches issued since the last call with reset != 0, measured with HIP
+ * events recorded around every stage launch on the domain's stream while
+ * timing is enabled (swe_enable_timing).  Synchronises. */
+int swe_enable_timing(swe_domain *d, int32_t on);
+int swe_stage_times(swe_domain *d, double *ms_stage1, double *ms_stage2, int64_t *launches,
+                    int32_t reset);
+
+void swe_destroy(swe_domain *d);
+const char *swe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

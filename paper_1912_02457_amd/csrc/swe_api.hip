@@ -1,0 +1,594 @@
+// Host side of the C ABI declared in include/swe.h: parameter validation,
+// workspace layout, uploads, launches, HIP-graph replay of step chunks and
+// kernel timing.  No exception crosses the ABI.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/swe.h"
+#include "swe_device.h"
+
+namespace swe {
+hipError_t launch_stage(int stage, bool proj, const Dom &d, const Tiling &T, int parity, double dt_fixed,
+                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_cfl(const Dom &d, int slot, hipStream_t s);
+hipError_t launch_ctrl_reset(Ctrl *c, double t, int slot, hipStream_t s);
+hipError_t launch_set_t_end(Ctrl *c, double te, hipStream_t s);
+hipError_t launch_diagnostics(const Dom &d, hipStream_t s);
+}  // namespace swe
+
+using namespace swe;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(SWE_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+int pitch_of(int n) { return (int)align_up((size_t)n, 64); }
+
+struct Layout {
+    size_t eta, hu, hv, eta1, hu1, hv1, Hc, f, north, fghost, nghost, alpha, bnd_t, bnd, wind_t, wind,
+        ctrl, partials, total;
+};
+
+Layout make_layout(const swe_params &p, int max_wind, int max_bnd)
+{
+    Layout L;
+    size_t plane = (size_t)p.ny * pitch_of(p.nx) * sizeof(float);
+    size_t cplane = (size_t)(p.ny + 1) * pitch_of(p.nx + 1) * sizeof(float);
+    size_t P = 2 * (size_t)p.ny + 2 * (size_t)p.nx;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, kAlign); return o; };
+    L.eta = take(plane); L.hu = take(plane); L.hv = take(plane);
+    L.eta1 = take(plane); L.hu1 = take(plane); L.hv1 = take(plane);
+    L.Hc = take(cplane);
+    L.f = take(plane);
+    L.north = p.north_projection ? take(plane) : take(0);
+    L.fghost = take(2 * P * sizeof(float));
+    L.nghost = take(2 * P * sizeof(float));
+    L.alpha = take(kMaxFrs * sizeof(float));
+    L.bnd_t = take((size_t)max_bnd * sizeof(double));
+    L.bnd = take((size_t)max_bnd * 3 * P * sizeof(float));
+    L.wind_t = take((size_t)max_wind * sizeof(double));
+    L.wind = take((size_t)max_wind * 2 * sizeof(float));
+    L.ctrl = take(sizeof(Ctrl));
+    L.partials = take(2 * (size_t)p.ny * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+int validate(const swe_params *p)
+{
+    if (!p) return fail(SWE_E_ARG, "params is NULL");
+    if (p->nx < 2 || p->ny < 2) return fail(SWE_E_ARG, "nx and ny must be >= 2");
+    if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(SWE_E_ARG, "domain too large");
+    if (!(std::isfinite(p->dx) && p->dx > 0 && std::isfinite(p->dy) && p->dy > 0))
+        return fail(SWE_E_ARG, "dx and dy must be finite and > 0");
+    if (!(std::isfinite(p->g) && p->g > 0)) return fail(SWE_E_ARG, "g must be > 0");
+    if (!(p->courant > 0 && p->courant <= 1)) return fail(SWE_E_ARG, "courant must be in (0, 1]");
+    if (!(p->theta >= 1 && p->theta <= 2)) return fail(SWE_E_ARG, "theta must be in [1, 2]");
+    if (!(std::isfinite(p->kappa) && p->kappa > 0)) return fail(SWE_E_ARG, "kappa must be > 0");
+    for (int k = 0; k < 4; ++k)
+        if (p->bc[k] < SWE_BC_WALL || p->bc[k] > SWE_BC_NESTED) return fail(SWE_E_ARG, "unknown boundary kind");
+    if ((p->bc[0] == SWE_BC_PERIODIC) != (p->bc[1] == SWE_BC_PERIODIC) ||
+        (p->bc[2] == SWE_BC_PERIODIC) != (p->bc[3] == SWE_BC_PERIODIC))
+        return fail(SWE_E_ARG, "periodic boundaries must be set on both sides of an axis");
+    if (p->friction < SWE_FRICTION_NONE || p->friction > SWE_FRICTION_MANNING)
+        return fail(SWE_E_ARG, "unknown friction law");
+    if (!(std::isfinite(p->friction_coeff) && p->friction_coeff >= 0))
+        return fail(SWE_E_ARG, "friction_coeff must be >= 0");
+    if (!(std::isfinite(p->rho_w) && p->rho_w > 0)) return fail(SWE_E_ARG, "rho_w must be > 0");
+    if (p->frs_width < 1 || p->frs_width > kMaxFrs) return fail(SWE_E_ARG, "frs_width must be in [1, 32]");
+    if (!(std::isfinite(p->frs_d0) && p->frs_d0 > 0)) return fail(SWE_E_ARG, "frs_d0 must be > 0");
+    if (p->north_projection != 0 && p->north_projection != 1) return fail(SWE_E_ARG, "north_projection must be 0 or 1");
+    return SWE_OK;
+}
+
+bool all_finite(const float *a, size_t n)
+{
+    for (size_t k = 0; k < n; ++k)
+        if (!std::isfinite(a[k])) return false;
+    return true;
+}
+
+bool any_nested(const swe_params &p)
+{
+    for (int k = 0; k < 4; ++k)
+        if (p.bc[k] == SWE_BC_NESTED) return true;
+    return false;
+}
+
+}  // namespace
+
+struct swe_domain {
+    swe_params p{};
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    char *ws = nullptr;
+    Layout L{};
+    Dom dom{};
+    Tiling T{};
+    int parity = 0;
+    int max_wind = 0, max_bnd = 0;
+    bool has_bnd = false;
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (steps, start parity)
+    std::vector<hipGraph_t> graph_objs;
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    int64_t timed_steps = 0;
+};
+
+namespace {
+
+int upload_pitched(swe_domain *d, size_t off, const float *src, int w, int h, int pitch, hipStream_t s)
+{
+    HIP_TRY(hipMemcpy2DAsync(d->ws + off, (size_t)pitch * sizeof(float), src, (size_t)w * sizeof(float),
+                             (size_t)w * sizeof(float), (size_t)h, hipMemcpyHostToDevice, s));
+    return SWE_OK;
+}
+
+// f of the two ghost layers of nested sides: the mirrored interior cell
+// (layer 0 <- the outermost interior cell, layer 1 <- the next one), with the
+// real f even where that cell is land.
+void build_ghost_table(const swe_params &p, const float *field, std::vector<float> &out)
+{
+    const int nx = p.nx, ny = p.ny, P = 2 * nx + 2 * ny;
+    out.assign(2 * (size_t)P, 0.f);
+    for (int layer = 0; layer < 2; ++layer) {
+        float *o = out.data() + (size_t)layer * P;
+        for (int j = 0; j < ny; ++j) {
+            o[j] = field ? field[(size_t)j * nx + layer] : 0.f;
+            o[ny + j] = field ? field[(size_t)j * nx + (nx - 1 - layer)] : 0.f;
+        }
+        for (int i = 0; i < nx; ++i) {
+            o[2 * ny + i] = field ? field[(size_t)layer * nx + i] : 0.f;
+            o[2 * ny + nx + i] = field ? field[(size_t)(ny - 1 - layer) * nx + i] : 0.f;
+        }
+    }
+}
+
+int reset_time_and_cfl(swe_domain *d, double t)
+{
+    d->parity = 0;
+    HIP_TRY(launch_ctrl_reset(d->dom.ctrl, t, 0, d->stream));
+    HIP_TRY(launch_cfl(d->dom, 0, d->stream));
+    return SWE_OK;
+}
+
+int copy_state_to_star(swe_domain *d)
+{
+    size_t plane = (size_t)d->p.ny * d->dom.pitch * sizeof(float);
+    HIP_TRY(hipMemcpyAsync(d->dom.eta1, d->dom.eta, plane, hipMemcpyDeviceToDevice, d->stream));
+    HIP_TRY(hipMemcpyAsync(d->dom.hu1, d->dom.hu, plane, hipMemcpyDeviceToDevice, d->stream));
+    HIP_TRY(hipMemcpyAsync(d->dom.hv1, d->dom.hv, plane, hipMemcpyDeviceToDevice, d->stream));
+    return SWE_OK;
+}
+
+int check_ready(swe_domain *d)
+{
+    if (!d) return fail(SWE_E_ARG, "domain is NULL");
+    if (any_nested(d->p) && !d->has_bnd) return fail(SWE_E_STATE, "nested boundary without boundary data");
+    return SWE_OK;
+}
+
+int launch_step(swe_domain *d, int parity, double dt_fixed, hipStream_t s, bool timed)
+{
+    bool proj = d->p.north_projection != 0;
+    if (timed) {
+        while (d->ev_pool.size() < d->ev_used + 4) {
+            hipEvent_t ev;
+            HIP_TRY(hipEventCreate(&ev));
+            d->ev_pool.push_back(ev);
+        }
+        hipEvent_t *pe = &d->ev_pool[d->ev_used];
+        HIP_TRY(launch_stage(1, proj, d->dom, d->T, parity, dt_fixed, s, pe[0], pe[1]));
+        HIP_TRY(launch_stage(2, proj, d->dom, d->T, parity, dt_fixed, s, pe[2], pe[3]));
+        d->ev_used += 4;
+        d->timed_steps += 1;
+        return SWE_OK;
+    }
+    HIP_TRY(launch_stage(1, proj, d->dom, d->T, parity, dt_fixed, s, nullptr, nullptr));
+    HIP_TRY(launch_stage(2, proj, d->dom, d->T, parity, dt_fixed, s, nullptr, nullptr));
+    return SWE_OK;
+}
+
+constexpr int kGraphChunk = 16;
+
+int get_graph(swe_domain *d, int steps, int parity, hipGraphExec_t *out)
+{
+    auto key = std::make_pair(steps, parity);
+    auto it = d->graphs.find(key);
+    if (it != d->graphs.end()) { *out = it->second; return SWE_OK; }
+    if (!d->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&d->capture_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(d->capture_stream, hipStreamCaptureModeThreadLocal));
+    int rc = SWE_OK;
+    for (int k = 0; k < steps && rc == SWE_OK; ++k) rc = launch_step(d, (parity + k) & 1, 0.0, d->capture_stream, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(d->capture_stream, &g);
+    if (rc != SWE_OK) { if (g) hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { hipGraphDestroy(g); return hip_fail(e, "hipGraphInstantiate"); }
+    d->graph_objs.push_back(g);
+    d->graphs[key] = ex;
+    *out = ex;
+    return SWE_OK;
+}
+
+int read_ctrl(swe_domain *d, Ctrl *c)
+{
+    HIP_TRY(hipMemcpyAsync(c, d->dom.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, d->stream));
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    return SWE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *swe_last_error(void) { return g_last_error.c_str(); }
+
+int swe_workspace_bytes(const swe_params *p, int32_t max_wind_times, int32_t max_bnd_times, size_t *bytes)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!bytes || max_wind_times < 1 || max_bnd_times < 0) return fail(SWE_E_ARG, "bad workspace query");
+    *bytes = make_layout(*p, max_wind_times, max_bnd_times).total;
+    return SWE_OK;
+}
+
+int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
+                    int32_t max_wind_times, int32_t max_bnd_times, const float *Hc, const uint8_t *land,
+                    const float *f, const float *theta, const float *eta, const float *hu, const float *hv,
+                    swe_domain **out)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!out || !Hc || !f || !eta || !hu || !hv || !dev_workspace) return fail(SWE_E_ARG, "NULL array");
+    if (max_wind_times < 1 || max_bnd_times < 0) return fail(SWE_E_ARG, "bad forcing bounds");
+    if (any_nested(*p) && max_bnd_times < 1) return fail(SWE_E_ARG, "nested sides need max_bnd_times >= 1");
+    if (((uintptr_t)dev_workspace) % kAlign) return fail(SWE_E_ARG, "workspace must be 256-byte aligned");
+    *out = nullptr;
+    const int nx = p->nx, ny = p->ny;
+    const size_t nc = (size_t)nx * ny, nk = (size_t)(nx + 1) * (ny + 1);
+    if (!all_finite(Hc, nk) || !all_finite(f, nc) || !all_finite(eta, nc) || !all_finite(hu, nc) ||
+        !all_finite(hv, nc) || (theta && !all_finite(theta, nc)))
+        return fail(SWE_E_ARG, "non-finite input");
+    if (p->bc[0] == SWE_BC_PERIODIC)
+        for (int j = 0; j <= ny; ++j)
+            if (Hc[(size_t)j * (nx + 1)] != Hc[(size_t)j * (nx + 1) + nx])
+                return fail(SWE_E_ARG, "periodic x: corner depths at x=0 and x=nx differ");
+    if (p->bc[2] == SWE_BC_PERIODIC)
+        for (int i = 0; i <= nx; ++i)
+            if (Hc[i] != Hc[(size_t)ny * (nx + 1) + i])
+                return fail(SWE_E_ARG, "periodic y: corner depths at y=0 and y=ny differ");
+    Layout L = make_layout(*p, max_wind_times, max_bnd_times);
+    if (bytes < L.total) return fail(SWE_E_NOMEM, "workspace too small");
+
+    swe_domain *d = new (std::nothrow) swe_domain();
+    if (!d) return fail(SWE_E_NOMEM, "host allocation failed");
+    d->p = *p;
+    d->stream = (hipStream_t)hip_stream;
+    d->ws = (char *)dev_workspace;
+    d->L = L;
+    d->max_wind = max_wind_times;
+    d->max_bnd = max_bnd_times;
+    d->has_bnd = false;
+
+    Dom &D = d->dom;
+    D.nx = nx; D.ny = ny;
+    D.pitch = pitch_of(nx);
+    D.cpitch = pitch_of(nx + 1);
+    D.P = 2 * nx + 2 * ny;
+    for (int k = 0; k < 4; ++k) D.bc[k] = p->bc[k];
+    D.dx = (float)p->dx; D.dy = (float)p->dy;
+    D.rdx = (float)(1.0 / p->dx); D.rdy = (float)(1.0 / p->dy);
+    D.kx = (float)(p->dx / (2.0 * p->g)); D.ky = (float)(p->dy / (2.0 * p->g));
+    D.g = (float)p->g; D.theta = (float)p->theta; D.kappa = (float)p->kappa;
+    D.inv2kappa = (float)(1.0 / (2.0 * p->kappa)); D.half_kappa = (float)(0.5 * p->kappa);
+    D.courant_q = (float)(0.25 * p->courant);
+    D.friction = p->friction;
+    D.fric_c = p->friction == SWE_FRICTION_MANNING ? (float)(p->g * p->friction_coeff * p->friction_coeff)
+                                                    : (float)p->friction_coeff;
+    D.inv_rho_w = 1.0 / p->rho_w;
+    D.g64 = p->g; D.kappa64 = p->kappa; D.dx64 = p->dx; D.dy64 = p->dy;
+    D.frs_w = any_nested(*p) ? p->frs_width : 0;
+    char *w = d->ws;
+    D.eta = (float *)(w + L.eta); D.hu = (float *)(w + L.hu); D.hv = (float *)(w + L.hv);
+    D.eta1 = (float *)(w + L.eta1); D.hu1 = (float *)(w + L.hu1); D.hv1 = (float *)(w + L.hv1);
+    D.Hc = (const float *)(w + L.Hc);
+    D.f = (const float *)(w + L.f);
+    D.north = p->north_projection ? (const float *)(w + L.north) : nullptr;
+    D.fghost = (const float *)(w + L.fghost);
+    D.nghost = (const float *)(w + L.nghost);
+    D.frs_alpha = (const float *)(w + L.alpha);
+    D.nb = 0; D.bnd_t = (const double *)(w + L.bnd_t); D.bnd = (const float *)(w + L.bnd);
+    D.nw = 0; D.wind_t = (const double *)(w + L.wind_t); D.wind = (const float *)(w + L.wind);
+    D.ctrl = (Ctrl *)(w + L.ctrl);
+    D.partials = (double *)(w + L.partials);
+    d->T = make_tiling(nx, ny, 16);
+
+    hipStream_t s = d->stream;
+    int r = SWE_OK;
+    // f with land encoded as NaN
+    std::vector<float> fl(f, f + nc);
+    if (land)
+        for (size_t k = 0; k < nc; ++k)
+            if (land[k]) fl[k] = std::nanf("");
+    std::vector<float> fg, ng, alpha(kMaxFrs, 0.f);
+    build_ghost_table(*p, f, fg);
+    build_ghost_table(*p, theta, ng);
+    for (int k = 0; k < kMaxFrs; ++k) alpha[k] = (float)(1.0 - std::tanh((double)k / p->frs_d0));
+    Ctrl c0{};
+    if ((r = upload_pitched(d, L.eta, eta, nx, ny, D.pitch, s)) ||
+        (r = upload_pitched(d, L.hu, hu, nx, ny, D.pitch, s)) ||
+        (r = upload_pitched(d, L.hv, hv, nx, ny, D.pitch, s)) ||
+        (r = upload_pitched(d, L.Hc, Hc, nx + 1, ny + 1, D.cpitch, s)) ||
+        (r = upload_pitched(d, L.f, fl.data(), nx, ny, D.pitch, s))) {
+        delete d;
+        return r;
+    }
+    if (p->north_projection) {
+        std::vector<float> th0(nc, 0.f);
+        if ((r = upload_pitched(d, L.north, theta ? theta : th0.data(), nx, ny, D.pitch, s))) { delete d; return r; }
+        hipStreamSynchronize(s);
+    }
+    hipError_t e;
+    if ((e = hipMemcpyAsync(w + L.fghost, fg.data(), fg.size() * sizeof(float), hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(w + L.nghost, ng.data(), ng.size() * sizeof(float), hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(w + L.alpha, alpha.data(), alpha.size() * sizeof(float), hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(w + L.ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice, s))) {
+        delete d;
+        return hip_fail(e, "upload");
+    }
+    // uniform zero wind until set
+    double wt0 = 0.0;
+    float w0[2] = {0.f, 0.f};
+    if ((e = hipMemcpyAsync(w + L.wind_t, &wt0, sizeof(double), hipMemcpyHostToDevice, s)) ||
+        (e = hipMemcpyAsync(w + L.wind, w0, sizeof(w0), hipMemcpyHostToDevice, s))) {
+        delete d;
+        return hip_fail(e, "upload");
+    }
+    D.nw = 1;
+    if ((r = copy_state_to_star(d)) || (r = reset_time_and_cfl(d, 0.0))) { delete d; return r; }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) { delete d; return hip_fail(e, "init sync"); }
+    *out = d;
+    return SWE_OK;
+}
+
+int swe_set_forcing(swe_domain *d, int32_t kind, int32_t n_times, const double *times, const float *data)
+{
+    if (!d || !times || !data || n_times < 1) return fail(SWE_E_ARG, "bad forcing arguments");
+    for (int k = 0; k < n_times; ++k) {
+        if (!std::isfinite(times[k])) return fail(SWE_E_ARG, "non-finite forcing time");
+        if (k > 0 && !(times[k] > times[k - 1])) return fail(SWE_E_ARG, "forcing times must increase");
+    }
+    char *w = d->ws;
+    hipStream_t s = d->stream;
+    if (kind == SWE_FORCING_WIND_STRESS) {
+        if (n_times > d->max_wind) return fail(SWE_E_ARG, "more wind snapshots than the workspace holds");
+        if (!all_finite(data, 2 * (size_t)n_times)) return fail(SWE_E_ARG, "non-finite wind data");
+        HIP_TRY(hipMemcpyAsync(w + d->L.wind_t, times, n_times * sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(w + d->L.wind, data, 2 * (size_t)n_times * sizeof(float), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        d->dom.nw = n_times;
+    } else if (kind == SWE_FORCING_BOUNDARY) {
+        size_t n = (size_t)n_times * 3 * d->dom.P;
+        if (n_times > d->max_bnd) return fail(SWE_E_ARG, "more boundary snapshots than the workspace holds");
+        if (!all_finite(data, n)) return fail(SWE_E_ARG, "non-finite boundary data");
+        HIP_TRY(hipMemcpyAsync(w + d->L.bnd_t, times, n_times * sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(w + d->L.bnd, data, n * sizeof(float), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        d->dom.nb = n_times;
+        d->has_bnd = true;
+    } else {
+        return fail(SWE_E_ARG, "unknown forcing kind");
+    }
+    // kernel arguments changed: captured graphs are stale
+    for (auto &kv : d->graphs) hipGraphExecDestroy(kv.second);
+    for (auto g : d->graph_objs) hipGraphDestroy(g);
+    d->graphs.clear();
+    d->graph_objs.clear();
+    return SWE_OK;
+}
+
+int swe_step(swe_domain *d, int32_t n_steps)
+{
+    int rc = check_ready(d);
+    if (rc) return rc;
+    if (n_steps < 0) return fail(SWE_E_ARG, "n_steps < 0");
+    int left = n_steps;
+    if (!d->timing) {
+        while (left >= kGraphChunk) {
+            hipGraphExec_t g;
+            if ((rc = get_graph(d, kGraphChunk, d->parity, &g))) return rc;
+            HIP_TRY(hipGraphLaunch(g, d->stream));
+            d->parity = (d->parity + kGraphChunk) & 1;
+            left -= kGraphChunk;
+        }
+    }
+    for (; left > 0; --left) {
+        if ((rc = launch_step(d, d->parity, 0.0, d->stream, d->timing))) return rc;
+        d->parity ^= 1;
+    }
+    return SWE_OK;
+}
+
+int swe_step_dt(swe_domain *d, int32_t n_steps, const double *dts)
+{
+    int rc = check_ready(d);
+    if (rc) return rc;
+    if (n_steps < 0 || (n_steps > 0 && !dts)) return fail(SWE_E_ARG, "bad dt sequence");
+    for (int k = 0; k < n_steps; ++k)
+        if (!(std::isfinite(dts[k]) && dts[k] > 0)) return fail(SWE_E_ARG, "dt must be finite and > 0");
+    for (int k = 0; k < n_steps; ++k) {
+        if ((rc = launch_step(d, d->parity, dts[k], d->stream, d->timing))) return rc;
+        d->parity ^= 1;
+    }
+    return SWE_OK;
+}
+
+int swe_run_until(swe_domain *d, double t_end, int64_t *steps_taken)
+{
+    int rc = check_ready(d);
+    if (rc) return rc;
+    if (!std::isfinite(t_end)) return fail(SWE_E_ARG, "t_end must be finite");
+    Ctrl c;
+    if ((rc = read_ctrl(d, &c))) return rc;
+    int64_t s0 = c.steps;
+    double t = c.t[d->parity];
+    if (t_end > t) {
+        HIP_TRY(launch_set_t_end(d->dom.ctrl, t_end, d->stream));
+        // estimate the remaining steps from the current dt, then check
+        const int chunk_max = 4096;
+        while (true) {
+            if ((rc = read_ctrl(d, &c))) break;
+            t = c.t[d->parity];
+            if (c.flags) break;
+            if (t >= t_end) break;
+            float wm;
+            uint32_t wb = c.wmax[d->parity];
+            std::memcpy(&wm, &wb, sizeof(wm));
+            double dt = wm > 0 ? (double)(d->dom.courant_q / wm) : 1.0;
+            double est = (t_end - t) / dt;
+            int n = (int)std::min<double>(chunk_max, std::max<double>(kGraphChunk, std::ceil(est * 1.05) + 1));
+            if ((rc = swe_step(d, n))) break;
+        }
+        HIP_TRY(launch_set_t_end(d->dom.ctrl, 0.0, d->stream));
+        if (rc) return rc;
+    }
+    if ((rc = read_ctrl(d, &c))) return rc;
+    if (steps_taken) *steps_taken = c.steps - s0;
+    if (c.flags) return fail(SWE_E_UNSTABLE, "non-finite state");
+    return SWE_OK;
+}
+
+int swe_read_state(swe_domain *d, float *eta, float *hu, float *hv, double *t, double *dt_next)
+{
+    if (!d) return fail(SWE_E_ARG, "domain is NULL");
+    const int nx = d->p.nx, ny = d->p.ny;
+    float *dst[3] = {eta, hu, hv};
+    float *src[3] = {d->dom.eta, d->dom.hu, d->dom.hv};
+    for (int k = 0; k < 3; ++k) {
+        if (!dst[k]) continue;
+        HIP_TRY(hipMemcpy2DAsync(dst[k], (size_t)nx * sizeof(float), src[k], (size_t)d->dom.pitch * sizeof(float),
+                                 (size_t)nx * sizeof(float), (size_t)ny, hipMemcpyDefault, d->stream));
+    }
+    Ctrl c;
+    int rc = read_ctrl(d, &c);
+    if (rc) return rc;
+    if (t) *t = c.t[d->parity];
+    if (dt_next) {
+        float wm;
+        uint32_t wb = c.wmax[d->parity];
+        std::memcpy(&wm, &wb, sizeof(wm));
+        *dt_next = wm > 0 ? (double)(d->dom.courant_q / wm) : INFINITY;
+    }
+    if (c.flags) return fail(SWE_E_UNSTABLE, "non-finite state");
+    return SWE_OK;
+}
+
+int swe_set_state(swe_domain *d, const float *eta, const float *hu, const float *hv, double t)
+{
+    if (!d || !eta || !hu || !hv) return fail(SWE_E_ARG, "NULL argument");
+    const int nx = d->p.nx, ny = d->p.ny;
+    size_t nc = (size_t)nx * ny;
+    if (!std::isfinite(t) || !all_finite(eta, nc) || !all_finite(hu, nc) || !all_finite(hv, nc))
+        return fail(SWE_E_ARG, "non-finite state");
+    int rc;
+    if ((rc = upload_pitched(d, d->L.eta, eta, nx, ny, d->dom.pitch, d->stream)) ||
+        (rc = upload_pitched(d, d->L.hu, hu, nx, ny, d->dom.pitch, d->stream)) ||
+        (rc = upload_pitched(d, d->L.hv, hv, nx, ny, d->dom.pitch, d->stream)) || (rc = copy_state_to_star(d)) ||
+        (rc = reset_time_and_cfl(d, t)))
+        return rc;
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    return SWE_OK;
+}
+
+int swe_diagnostics(swe_domain *d, double *mass, double *energy)
+{
+    if (!d) return fail(SWE_E_ARG, "domain is NULL");
+    HIP_TRY(launch_diagnostics(d->dom, d->stream));
+    Ctrl c;
+    int rc = read_ctrl(d, &c);
+    if (rc) return rc;
+    if (mass) *mass = c.mass;
+    if (energy) *energy = c.energy;
+    return SWE_OK;
+}
+
+int swe_status(swe_domain *d)
+{
+    if (!d) return fail(SWE_E_ARG, "domain is NULL");
+    Ctrl c;
+    int rc = read_ctrl(d, &c);
+    if (rc) return rc;
+    return c.flags ? fail(SWE_E_UNSTABLE, "non-finite state") : SWE_OK;
+}
+
+int swe_enable_timing(swe_domain *d, int32_t on)
+{
+    if (!d) return fail(SWE_E_ARG, "domain is NULL");
+    d->timing = on != 0;
+    return SWE_OK;
+}
+
+int swe_stage_times(swe_domain *d, double *ms_stage1, double *ms_stage2, int64_t *launches, int32_t reset)
+{
+    if (!d) return fail(SWE_E_ARG, "domain is NULL");
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    double a = 0, b = 0;
+    for (size_t k = 0; k + 3 < d->ev_used; k += 4) {
+        float x = 0, y = 0;
+        HIP_TRY(hipEventElapsedTime(&x, d->ev_pool[k], d->ev_pool[k + 1]));
+        HIP_TRY(hipEventElapsedTime(&y, d->ev_pool[k + 2], d->ev_pool[k + 3]));
+        a += x;
+        b += y;
+    }
+    int64_t n = d->timed_steps;
+    if (ms_stage1) *ms_stage1 = n ? a / n : 0.0;
+    if (ms_stage2) *ms_stage2 = n ? b / n : 0.0;
+    if (launches) *launches = n;
+    if (reset) {
+        d->ev_used = 0;
+        d->timed_steps = 0;
+    }
+    return SWE_OK;
+}
+
+void swe_destroy(swe_domain *d)
+{
+    if (!d) return;
+    if (d->stream) hipStreamSynchronize(d->stream);
+    for (auto &kv : d->graphs) hipGraphExecDestroy(kv.second);
+    for (auto g : d->graph_objs) hipGraphDestroy(g);
+    for (auto e : d->ev_pool) hipEventDestroy(e);
+    if (d->capture_stream) hipStreamDestroy(d->capture_stream);
+    delete d;
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// Device-side data structures of the gfx950 shallow-water stage kernels.
+//
+// One domain lives in a caller-provided device workspace:
+//   state Q^n (eta, hu, hv) and Q* as float32 planes [ny][pitch], pitch a
+//   multiple of 64 floats (256 B rows), the corner depths [ny+1][cpitch], the
+//   Coriolis plane f [ny][pitch] in which NaN marks a land cell (the static
+//   mask costs no extra bytes, as in the section "Moving wet-dry boundary and
+//   land mask"), small forcing tables and a control block holding the time,
+//   the CFL accumulators and the error flag.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swe {
+
+enum { BC_WALL = 0, BC_PERIODIC = 1, BC_NESTED = 2 };
+enum { FR_NONE = 0, FR_LINEAR = 1, FR_QUADRATIC = 2, FR_MANNING = 3 };
+
+constexpr int kWave = 64;                  // wavefront width on CDNA
+constexpr int kHalo = 2;                   // stencil reach: slope of the neighbour's face value
+constexpr int kStrip = kWave - 2 * kHalo;  // output columns per wave
+constexpr int kWavesPerBlock = 4;
+constexpr int kMaxFrs = 32;
+
+// Control block; the time and the CFL accumulator are double-buffered by
+// step parity so that both stage kernels of a step read the same values
+// while the next step's slots are being produced.
+struct Ctrl {
+    double t[2];         // time at the start of the step of each parity
+    uint32_t wmax[2];    // max over non-land cells of max((|u|+c)/dx, (|v|+c)/dy), float bits
+    uint32_t flags;      // bit 0: non-finite state produced
+    float dt_last;       // dt of the last step taken
+    int64_t steps;       // steps taken (no-op steps past t_end excluded)
+    double t_end;        // > 0: clamp steps to end exactly at t_end, skip steps after it
+    double mass, energy; // results of the diagnostics reduction
+    double pad[2];
+};
+
+// Everything a stage kernel needs, passed by value.
+struct Dom {
+    int nx, ny, pitch, cpitch, P;  // P = 2 ny + 2 nx perimeter cells
+    int bc[4];                     // W, E, S, N
+    float dx, dy, rdx, rdy, kx, ky; // kx = dx / (2 g)
+    float g, theta, kappa, inv2kappa, half_kappa, courant_q; // courant_q = C / 4
+    int friction;
+    float fric_c;                  // r, r, or g n^2 (Manning)
+    double inv_rho_w;
+    double g64, kappa64, dx64, dy64;  // float64 copies for the diagnostics reductions
+    int frs_w;
+    float *eta, *hu, *hv;          // Q^n, updated in place by stage 2
+    float *eta1, *hu1, *hv1;       // Q*
+    const float *Hc, *f, *north;
+    const float *fghost, *nghost;  // [2 layers][P] f and north angle of nested ghost cells
+    const float *frs_alpha;        // [kMaxFrs] 1 - tanh(d / d0)
+    int nb;                        // boundary snapshots
+    const double *bnd_t;
+    const float *bnd;              // [nb][3][P]
+    int nw;                        // wind snapshots
+    const double *wind_t;
+    const float *wind;             // [nw][2]
+    Ctrl *ctrl;
+    double *partials;              // diagnostics partial sums
+};
+
+struct Tiling {
+    int by;       // rows per wave
+    int nstrips;  // ceil(nx / kStrip)
+    int nrb;      // ceil(ny / by)
+    int ntiles;   // nstrips * nrb
+    int nblocks;  // ceil(ntiles / kWavesPerBlock)
+};
+
+inline Tiling make_tiling(int nx, int ny, int by)
+{
+    Tiling t;
+    t.by = by;
+    t.nstrips = (nx + kStrip - 1) / kStrip;
+    t.nrb = (ny + by - 1) / by;
+    t.ntiles = t.nstrips * t.nrb;
+    t.nblocks = (t.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    return t;
+}
+
+}  // namespace swe

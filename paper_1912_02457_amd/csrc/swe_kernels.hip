@@ -1,0 +1,661 @@
+// Stage kernels of the eta-based, well-balanced central-upwind scheme
+// (Brodtkorb & Holm, arXiv 1912.02457) for gfx950.
+//
+// Work decomposition: one wavefront owns a strip of 64 consecutive columns
+// (60 output columns plus a 2-column halo on each side) and marches down a
+// block of rows with a sliding register window.  Neighbours along x come from
+// the adjacent lanes (cross-lane shuffles), neighbours along y from the rows
+// kept in registers, so every face flux is evaluated once and reused by the
+// two cells that share the face, and no LDS is needed.  Global loads are
+// 64-float (256 B) row segments.  Ghost cells are produced at load time from
+// the boundary kinds (no ghost kernel).
+//
+// Arithmetic follows the paper in float32 with two exact rewritings:
+//   * the rest-state pressure g R_f^2/2 with R_f = max(H_f, 0) is taken out
+//     of the pressure flux g h_f^2/2 and out of the bathymetry source
+//     (g/2dx)(h^E + h^W)(H_E - H_W); the two parts cancel exactly, so M is
+//     unchanged, but the float32 flux difference no longer carries the
+//     cancellation of g H^2/2 ~ 4e7 at 3000 m (section "Accuracy, precision
+//     and GPUs" motivates eta for the same reason).  Where both faces of a
+//     cell are below the datum the source becomes (g/dx) eta (H_E - H_W)
+//     (eta^E + eta^W = 2 eta); above the datum (dry land, H < 0) nothing is
+//     subtracted and a dry cell stays exactly at rest;
+//   * the north-vector projection of the Coriolis term (section "Coriolis
+//     force") returns f (hv, -hu) for every angle; the default variant uses
+//     that identity, PROJ = true evaluates the projection literally.
+#include <hip/hip_ext.h>
+
+#include "swe_device.h"
+
+namespace swe {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// value held by lane-1 / lane+1 (edge lanes get an unspecified value; they
+// are halo lanes whose results are never stored)
+__device__ __forceinline__ float from_left(float v) { return __shfl_up(v, 1, kWave); }
+__device__ __forceinline__ float from_right(float v) { return __shfl_down(v, 1, kWave); }
+__device__ __forceinline__ int from_left(int v) { return __shfl_up(v, 1, kWave); }
+__device__ __forceinline__ int from_right(int v) { return __shfl_down(v, 1, kWave); }
+
+// eq. desing_ours
+__device__ __forceinline__ float desing(float h, const Dom &d)
+{
+    float a = fabsf(h);
+    float lo = fminf(fmaf(h * h, d.inv2kappa, d.half_kappa), d.kappa);
+    float m = fmaxf(a, lo);
+    return h < 0.f ? -m : m;
+}
+
+// generalized minmod of theta*backward, central, theta*forward differences
+__device__ __forceinline__ float limited(float dm, float dp, float th)
+{
+    float a = th * dm, b = 0.5f * (dm + dp), c = th * dp;
+    float mn = fminf(a, fminf(b, c)), mx = fmaxf(a, fmaxf(b, c));
+    return mn > 0.f ? mn : (mx < 0.f ? mx : 0.f);
+}
+
+__device__ __forceinline__ void time_weights(int n, const double *ts, double tau, int &k, double &s)
+{
+    if (n <= 1 || tau <= ts[0]) { k = 0; s = 0.0; return; }
+    if (tau >= ts[n - 1]) { k = n - 2; s = 1.0; return; }
+    int a = 0;
+    while (a < n - 2 && ts[a + 1] <= tau) ++a;
+    k = a;
+    s = (tau - ts[a]) / (ts[a + 1] - ts[a]);
+}
+
+__device__ __forceinline__ float ext_value(const Dom &d, int k, double s, int fld, int idx)
+{
+    const float *a = d.bnd + ((size_t)k * 3 + fld) * d.P;
+    if (d.nb == 1) return a[idx];
+    const float *b = a + (size_t)3 * d.P;
+    return (float)((1.0 - s) * (double)a[idx] + s * (double)b[idx]);
+}
+
+__device__ __forceinline__ void wind_at(const Dom &d, double tau, float &wx, float &wy)
+{
+    if (d.nw <= 0) { wx = wy = 0.f; return; }
+    int k; double s;
+    time_weights(d.nw, d.wind_t, tau, k, s);
+    double ax = d.wind[2 * k], ay = d.wind[2 * k + 1];
+    if (d.nw > 1) {
+        ax = (1.0 - s) * ax + s * (double)d.wind[2 * k + 2];
+        ay = (1.0 - s) * ay + s * (double)d.wind[2 * k + 3];
+    }
+    wx = (float)(ax * d.inv_rho_w);
+    wy = (float)(ay * d.inv_rho_w);
+}
+
+struct CellIn { float e, u, v, f, th; };
+
+// Cell (i, r) with i in [-2, nx+1], r in [-2, ny+1], at most one of them
+// outside the domain.  Wall ghosts mirror the state with the normal momentum
+// and f negated (eq. tradWallBCx and f(-x) = -f(x) of eq. KxWallBCReq);
+// periodic ghosts wrap; nested ghosts take the external state at the stage
+// time and the f / north angle stored for them at init.
+template <bool PROJ>
+__device__ __forceinline__ CellIn load_cell(const Dom &d, const float *__restrict__ E,
+                                            const float *__restrict__ U, const float *__restrict__ V,
+                                            int i, int r, int bk, double bs)
+{
+    const int nx = d.nx, ny = d.ny;
+    int ci = i, cr = r, side = -1, idx = 0, layer = 0;
+    float su = 1.f, sv = 1.f, sf = 1.f;
+    if (i < 0) {
+        if (d.bc[0] == BC_PERIODIC) ci = i + nx;
+        else { ci = -1 - i; if (d.bc[0] == BC_WALL) { su = -1.f; sf = -1.f; } else { side = 0; idx = r; layer = -1 - i; } }
+    } else if (i >= nx) {
+        if (d.bc[1] == BC_PERIODIC) ci = i - nx;
+        else { ci = 2 * nx - 1 - i; if (d.bc[1] == BC_WALL) { su = -1.f; sf = -1.f; } else { side = 1; idx = ny + r; layer = i - nx; } }
+    } else if (r < 0) {
+        if (d.bc[2] == BC_PERIODIC) cr = r + ny;
+        else { cr = -1 - r; if (d.bc[2] == BC_WALL) { sv = -1.f; sf = -1.f; } else { side = 2; idx = 2 * ny + i; layer = -1 - r; } }
+    } else if (r >= ny) {
+        if (d.bc[3] == BC_PERIODIC) cr = r - ny;
+        else { cr = 2 * ny - 1 - r; if (d.bc[3] == BC_WALL) { sv = -1.f; sf = -1.f; } else { side = 3; idx = 2 * ny + nx + i; layer = r - ny; } }
+    }
+    CellIn c;
+    if (side >= 0) {
+        c.e = ext_value(d, bk, bs, 0, idx);
+        c.u = ext_value(d, bk, bs, 1, idx);
+        c.v = ext_value(d, bk, bs, 2, idx);
+        c.f = d.fghost[(size_t)layer * d.P + idx];
+        c.th = PROJ ? d.nghost[(size_t)layer * d.P + idx] : 0.f;
+    } else {
+        size_t o = (size_t)cr * d.pitch + ci;
+        c.e = E[o];
+        c.u = su * U[o];
+        c.v = sv * V[o];
+        c.f = sf * d.f[o];
+        c.th = PROJ ? d.north[o] : 0.f;
+    }
+    return c;
+}
+
+__device__ __forceinline__ int map_corner(int c, int n, int lo, int hi)
+{
+    if (c < 0) return lo == BC_PERIODIC ? c + n : -c;
+    if (c > n) return hi == BC_PERIODIC ? c - n : 2 * n - c;
+    return c;
+}
+
+__device__ __forceinline__ float corner(const Dom &d, int ci, int cj)
+{
+    int a = map_corner(ci, d.nx, d.bc[0], d.bc[1]);
+    int b = map_corner(cj, d.ny, d.bc[2], d.bc[3]);
+    return d.Hc[(size_t)b * d.cpitch + a];
+}
+
+struct F3 { float e, p, q; };
+
+// eq. numerical_flux for a face with depth Hf between a left state (eL,pL,qL)
+// and a right state; p is the momentum normal to the face, q the transverse
+// one.  Desingularised velocities, face momenta recomputed as h u, wave
+// speeds a+ >= 0 >= a-, transverse momentum upwinded on the mass flux.
+// The pressure uses the perturbation form (see the file header).
+__device__ __forceinline__ F3 cu_flux(float eL, float pL0, float qL0, float eR, float pR0, float qR0,
+                                      float Hf, const Dom &d)
+{
+    float hL = eL + Hf, hR = eR + Hf;
+    float rL = rcp(desing(hL, d)), rR = rcp(desing(hR, d));
+    float uL = pL0 * rL, vL = qL0 * rL, uR = pR0 * rR, vR = qR0 * rR;
+    float pL = hL * uL, pR = hR * uR;
+    float cL = fsqrt(d.g * fmaxf(hL, 0.f)), cR = fsqrt(d.g * fmaxf(hR, 0.f));
+    float ap = fmaxf(fmaxf(uL + cL, uR + cR), 0.f);
+    float am = fminf(fminf(uL - cL, uR - cR), 0.f);
+    // g (h_f^2 - R_f^2) / 2 = g/2 (eta_f + min(H_f,0)) (eta_f + H_f + max(H_f,0))
+    float Hn = fminf(Hf, 0.f), Hs2 = Hf + fmaxf(Hf, 0.f);
+    float PL = 0.5f * d.g * (eL + Hn) * (eL + Hs2), PR = 0.5f * d.g * (eR + Hn) * (eR + Hs2);
+    float FL = fmaf(pL, uL, PL), FR = fmaf(pR, uR, PR);
+    float den = ap - am;
+    F3 r;
+    if (den > 0.f) {
+        float w = rcp(den), aw = ap * am * w;
+        r.e = (ap * pL - am * pR) * w + aw * (eR - eL);
+        r.p = (ap * FL - am * FR) * w + aw * (pR - pL);
+        r.q = r.e * (r.e >= 0.f ? vL : vR);
+    } else {
+        r.e = 0.5f * (pL + pR);
+        r.p = 0.5f * (FL + FR);
+        r.q = 0.5f * (pL * vL + pR * vR);
+    }
+    return r;
+}
+
+// face with the land rule: a face touching land carries the reflective-wall
+// flux of its wet side; a face between two land cells carries nothing
+__device__ __forceinline__ F3 face_flux(float eL, float pL, float qL, float eR, float pR, float qR,
+                                        bool lL, bool lR, float Hf, const Dom &d)
+{
+    float e2R = lR ? eL : eR, p2R = lR ? -pL : pR, q2R = lR ? qL : qR;
+    float e2L = lL ? eR : eL, p2L = lL ? -pR : pL, q2L = lL ? qR : qL;
+    F3 r = cu_flux(e2L, p2L, q2L, e2R, p2R, q2R, Hf, d);
+    if (lL && lR) r.e = r.p = r.q = 0.f;
+    return r;
+}
+
+// bathymetry source times dx (x) or dy (y): (g/2)(h^E + h^W)(H_E - H_W)
+// minus g (R_E^2 - R_W^2)/2, R = max(H, 0), matching the pressure flux of
+// cu_flux.  With both faces below the datum it is g eta (H_E - H_W).
+__device__ __forceinline__ float bathy_source(float eta, float eE, float eW, float HE, float HW, const Dom &d)
+{
+    float deep = d.g * eta * (HE - HW);
+    float RE = fmaxf(HE, 0.f), RW = fmaxf(HW, 0.f);
+    float gen = 0.5f * d.g * (((eE + HE) + (eW + HW)) * (HE - HW) - (RE * RE - RW * RW));
+    return (HE >= 0.f && HW >= 0.f) ? deep : gen;
+}
+
+// bed shear stress coefficient S >= 0, the source being -S (hu, hv)
+__device__ __forceinline__ float friction_coeff(const Dom &d, float h, float hu, float hv)
+{
+    if (d.friction == FR_NONE) return 0.f;
+    float a = fabsf(desing(h, d));
+    float ra = rcp(a);
+    if (d.friction == FR_LINEAR) return d.fric_c * ra;
+    float speed = fsqrt(hu * hu + hv * hv) * ra;
+    if (d.friction == FR_QUADRATIC) return d.fric_c * speed * ra * ra;
+    // Manning: g n^2 |u| / a^(4/3)
+    float a43 = __builtin_amdgcn_exp2f((4.0f / 3.0f) * __builtin_amdgcn_logf(a));
+    return d.fric_c * speed * rcp(a43);
+}
+
+// One row of cells of the sliding window (per lane: column i).
+struct Row {
+    float e, u, v, f;    // state (ghost-resolved) and Coriolis parameter
+    float cx, cy;        // Coriolis terms of the reconstruction (f v, -f u)
+    float cn0, cn1;      // corner depths at (i, r+1), (i+1, r+1)
+    float Hw, He, Hs, Hn, Hb;
+    int land;
+    float dmL, dmU, dmV; // y backward differences (this row minus the row below)
+};
+
+template <bool PROJ>
+__device__ __forceinline__ void cell_terms(Row &R, float cs0, float cs1, float th, const Dom &d)
+{
+    R.Hw = 0.5f * (cs0 + R.cn0);
+    R.He = 0.5f * (cs1 + R.cn1);
+    R.Hs = 0.5f * (cs0 + cs1);
+    R.Hn = 0.5f * (R.cn0 + R.cn1);
+    R.Hb = 0.25f * ((cs0 + R.cn0) + (cs1 + R.cn1));
+    float h = R.e + R.Hb;
+    float ri = rcp(desing(h, d));
+    float uu = R.u * ri, vv = R.v * ri;
+    R.land = isnan(R.f) ? 1 : 0;
+    if (PROJ) {
+        float c = __cosf(th), s = __sinf(th);
+        float ue = c * uu - s * vv, vn = s * uu + c * vv;
+        R.cx = R.f * (c * vn - s * ue);
+        R.cy = R.f * (-s * vn - c * ue);
+    } else {
+        R.cx = R.f * vv;
+        R.cy = -R.f * uu;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stage kernel
+//   STAGE 1: Q* = (Q^n + dt M(Q^n)) / (1 + dt S(Q^n))               (momenta)
+//   STAGE 2: Q^{n+1} = (Q^n + Q* + dt M(Q*)) / 2 / (1 + dt/2 S(Q*))  (momenta)
+//            then flow relaxation (eq. frs) and the CFL reduction for the
+//            next step (eq. cfl)
+// eq. rk2_semiimp; M is eq. sw_semidiscrete with the sources of eq. swe.
+// ---------------------------------------------------------------------------
+template <int STAGE, bool PROJ>
+__global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Tiling T, int parity,
+                                                                      double dt_fixed)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    // Blocks are dispatched round-robin over the 8 XCDs: give each XCD a
+    // contiguous range of tiles so vertically adjacent tiles (which share
+    // halo rows) meet in the same L2.
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int q8 = nb >> 3, r8 = nb & 7, x8 = b & 7;
+    const int L = x8 * q8 + min(x8, r8) + (b >> 3);
+    const int tile = L * kWavesPerBlock + wid;
+
+    Ctrl *ctrl = d.ctrl;
+    const double tn = ctrl->t[parity];
+    const uint32_t wbits = ctrl->wmax[parity];
+    const double te = ctrl->t_end;
+    double dtd = dt_fixed > 0.0 ? dt_fixed : (double)(d.courant_q / __uint_as_float(wbits));
+    bool skip = false, last = false;
+    if (te > 0.0) {
+        if (tn >= te) skip = true;
+        else if (dtd >= te - tn) { dtd = te - tn; last = true; }
+    }
+    if (STAGE == 1 && b == 0 && threadIdx.x == 0) {
+        if (skip) {
+            ctrl->t[parity ^ 1] = tn;
+            ctrl->wmax[parity ^ 1] = wbits;
+        } else {
+            ctrl->t[parity ^ 1] = last ? te : tn + dtd;
+            ctrl->wmax[parity ^ 1] = 0u;
+            ctrl->dt_last = (float)dtd;
+            ctrl->steps += 1;
+        }
+    }
+    if (skip || tile >= T.ntiles) return;
+
+    const float dt = (float)dtd;
+    const double tau = STAGE == 1 ? tn : tn + dtd;
+    int bk = 0;
+    double bs = 0.0;
+    if (d.nb > 0) time_weights(d.nb, d.bnd_t, tau, bk, bs);
+    float wx, wy;
+    wind_at(d, tau, wx, wy);
+
+    const float *__restrict__ E = STAGE == 1 ? d.eta : d.eta1;
+    const float *__restrict__ U = STAGE == 1 ? d.hu : d.hu1;
+    const float *__restrict__ V = STAGE == 1 ? d.hv : d.hv1;
+
+    const int nx = d.nx, ny = d.ny;
+    const int strip = tile / T.nrb, rb = tile - strip * T.nrb;
+    const int x0 = strip * kStrip;
+    const int y0 = rb * T.by, y1 = min(y0 + T.by, ny);
+    const int i = x0 - kHalo + lane;
+    const int il = min(i, nx + 1);  // lanes right of the east ghosts load a ghost column
+    const bool xin = il >= 0 && il < nx;
+    const bool out_lane = lane >= kHalo && lane < kWave - kHalo && i < nx;
+    const float th = d.theta;
+
+    // Lanes in a ghost column only ever contribute rows inside [0, ny); their
+    // rows outside (diagonal ghosts) are clamped to stay in bounds and are
+    // never used.  Corner rows are clamped separately so that row 0 still
+    // sees corner row 0 as its south side.
+    auto load_row = [&](int r, Row &R, float &thv) {
+        int rr = xin ? r : min(max(r, 0), ny - 1);
+        int rc = xin ? r + 1 : min(max(r + 1, 0), ny);
+        CellIn c = load_cell<PROJ>(d, E, U, V, il, rr, bk, bs);
+        R.e = c.e; R.u = c.u; R.v = c.v; R.f = c.f;
+        thv = c.th;
+        R.cn0 = corner(d, il, rc);
+        R.cn1 = corner(d, il + 1, rc);
+    };
+
+    float wmax_loc = 0.f;
+    int bad = 0;
+
+    // window: A = row k-2 (output), B = row k-1, C = row k (just loaded)
+    Row A, B, C;
+    float csA0, csA1;           // south corners of the row being loaded
+    float eNA = 0.f, uNA = 0.f, vNA = 0.f; // north face values of row k-2 (from the previous iteration)
+    float eSA = 0.f;                       // south face eta of row k-2
+    F3 Gs = {0.f, 0.f, 0.f};    // flux through the south face of the output row
+
+    {
+        int rc = xin ? y0 - 2 : min(max(y0 - 2, 0), ny);
+        csA0 = corner(d, il, rc);
+        csA1 = corner(d, il + 1, rc);
+    }
+
+    for (int k = y0 - 2; k <= y1 + 1; ++k) {
+        float thv;
+        load_row(k, C, thv);
+        cell_terms<PROJ>(C, csA0, csA1, thv, d);
+        csA0 = C.cn0;
+        csA1 = C.cn1;
+        if (k >= y0 - 1) {
+            C.dmL = C.e - B.e - d.ky * (B.cy + C.cy);
+            C.dmU = C.u - B.u;
+            C.dmV = C.v - B.v;
+        }
+        if (k >= y0) {
+            // y-slopes and N/S face values of row k-1 (eqs. Kbackwards, hE for L)
+            float sL = limited(B.dmL, C.dmL, th);
+            float sU = limited(B.dmU, C.dmU, th);
+            float sV = limited(B.dmV, C.dmV, th);
+            if (A.land || C.land) sL = sU = sV = 0.f;
+            float rho = 0.5f * sL + d.ky * B.cy;
+            float eN = B.e + rho, eS = B.e - rho;
+            if (eN + B.Hn < 0.f) { eN = -B.Hn; eS = 2.f * B.e - eN; }
+            if (eS + B.Hs < 0.f) { eS = -B.Hs; eN = 2.f * B.e - eS; }
+            float uN = B.u + 0.5f * sU, uS = B.u - 0.5f * sU;
+            float vN = B.v + 0.5f * sV, vS = B.v - 0.5f * sV;
+            F3 Gn = {0.f, 0.f, 0.f};
+            if (k >= y0 + 1) {
+                // y-face between rows k-2 and k-1: normal momentum hv, transverse hu
+                Gn = face_flux(eNA, vNA, uNA, eS, vS, uS, A.land, B.land, B.Hs, d);
+            }
+            if (k >= y0 + 2) {
+                // ---- output row o = k-2 (record A) ----
+                const int o = k - 2;
+                const float eNA_out = eNA, eSA_out = eSA;
+                float eL = from_left(A.e), cxL = from_left(A.cx);
+                float uL = from_left(A.u), vL = from_left(A.v);
+                int landL = from_left(A.land), landR = from_right(A.land);
+                float dmK = A.e - eL - d.kx * (cxL + A.cx);
+                float dmU = A.u - uL, dmV = A.v - vL;
+                float sK = limited(dmK, from_right(dmK), th);
+                float sUx = limited(dmU, from_right(dmU), th);
+                float sVx = limited(dmV, from_right(dmV), th);
+                if (landL || landR) sK = sUx = sVx = 0.f;
+                float rx = 0.5f * sK + d.kx * A.cx;
+                float eE = A.e + rx, eW = A.e - rx;
+                if (eE + A.He < 0.f) { eE = -A.He; eW = 2.f * A.e - eE; }
+                if (eW + A.Hw < 0.f) { eW = -A.Hw; eE = 2.f * A.e - eW; }
+                float uE = A.u + 0.5f * sUx, uW = A.u - 0.5f * sUx;
+                float vE = A.v + 0.5f * sVx, vW = A.v - 0.5f * sVx;
+                F3 Fe = face_flux(eE, uE, vE, from_right(eW), from_right(uW), from_right(vW),
+                                  A.land != 0, landR != 0, A.He, d);
+                float Fwe = from_left(Fe.e), Fwp = from_left(Fe.p), Fwq = from_left(Fe.q);
+
+                if (out_lane && !A.land) {
+                    float Cx, Cy;
+                    if (PROJ) {
+                        float c = __cosf(d.north[(size_t)o * d.pitch + i]);
+                        float s = __sinf(d.north[(size_t)o * d.pitch + i]);
+                        float hue = c * A.u - s * A.v, hvn = s * A.u + c * A.v;
+                        Cx = A.f * (c * hvn - s * hue);
+                        Cy = A.f * (-s * hvn - c * hue);
+                    } else {
+                        Cx = A.f * A.v;
+                        Cy = -A.f * A.u;
+                    }
+                    float Me = -(Fe.e - Fwe) * d.rdx - (Gn.e - Gs.e) * d.rdy;
+                    float Mu = -(Fe.p - Fwp) * d.rdx - (Gn.q - Gs.q) * d.rdy +
+                               bathy_source(A.e, eE, eW, A.He, A.Hw, d) * d.rdx + Cx + wx;
+                    float Mv = -(Fe.q - Fwq) * d.rdx - (Gn.p - Gs.p) * d.rdy +
+                               bathy_source(A.e, eNA_out, eSA_out, A.Hn, A.Hs, d) * d.rdy + Cy + wy;
+                    const size_t oo = (size_t)o * d.pitch + i;
+                    float en, un, vn;
+                    if (STAGE == 1) {
+                        float S = friction_coeff(d, A.e + A.Hb, A.u, A.v);
+                        float den = rcp(1.f + dt * S);
+                        en = A.e + dt * Me;
+                        un = (A.u + dt * Mu) * den;
+                        vn = (A.v + dt * Mv) * den;
+                        d.eta1[oo] = en;
+                        d.hu1[oo] = un;
+                        d.hv1[oo] = vn;
+                    } else {
+                        float S = friction_coeff(d, A.e + A.Hb, A.u, A.v);
+                        float den = rcp(1.f + 0.5f * dt * S);
+                        float e0 = d.eta[oo], u0 = d.hu[oo], v0 = d.hv[oo];
+                        en = 0.5f * (e0 + (A.e + dt * Me));
+                        un = 0.5f * (u0 + (A.u + dt * Mu)) * den;
+                        vn = 0.5f * (v0 + (A.v + dt * Mv)) * den;
+                        if (d.frs_w > 0) {
+                            // eq. frs: nearest nested side within the zone, ties W, E, S, N
+                            int dist[4] = {i, nx - 1 - i, o, ny - 1 - o};
+                            int idxs[4] = {o, ny + o, 2 * ny + i, 2 * ny + nx + i};
+                            int best = -1, dd = 0;
+#pragma unroll
+                            for (int s = 0; s < 4; ++s)
+                                if (d.bc[s] == BC_NESTED && (best < 0 || dist[s] < dd)) { best = s; dd = dist[s]; }
+                            if (best >= 0 && dd < d.frs_w) {
+                                int idx = best == 0 ? idxs[0] : best == 1 ? idxs[1] : best == 2 ? idxs[2] : idxs[3];
+                                float al = d.frs_alpha[dd];
+                                en = (1.f - al) * en + al * ext_value(d, bk, bs, 0, idx);
+                                un = (1.f - al) * un + al * ext_value(d, bk, bs, 1, idx);
+                                vn = (1.f - al) * vn + al * ext_value(d, bk, bs, 2, idx);
+                            }
+                        }
+                        d.eta[oo] = en;
+                        d.hu[oo] = un;
+                        d.hv[oo] = vn;
+                        // eq. cfl on the new state
+                        float h = en + A.Hb;
+                        float ri = rcp(desing(h, d));
+                        float c = fsqrt(d.g * fmaxf(h, 0.f));
+                        float w = fmaxf((fabsf(un * ri) + c) * d.rdx, (fabsf(vn * ri) + c) * d.rdy);
+                        wmax_loc = fmaxf(wmax_loc, w);
+                        if (!(isfinite(en) && isfinite(un) && isfinite(vn))) bad = 1;
+                    }
+                }
+                Gs = Gn;
+            } else {
+                Gs = Gn;
+            }
+            eNA = eN; uNA = uN; vNA = vN;
+            eSA = eS;
+        }
+        A = B;
+        B = C;
+    }
+
+    if (STAGE == 2) {
+        for (int off = kWave / 2; off > 0; off >>= 1) wmax_loc = fmaxf(wmax_loc, __shfl_xor(wmax_loc, off, kWave));
+        unsigned long long anybad = __ballot(bad);
+        if (lane == 0) {
+            atomicMax(&ctrl->wmax[parity ^ 1], __float_as_uint(wmax_loc));
+            if (anybad) atomicOr(&ctrl->flags, 1u);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CFL reduction of a given state into ctrl->wmax[slot] (used at init and
+// after a state change); one thread per cell.
+// ---------------------------------------------------------------------------
+__global__ void cfl_kernel(Dom d, int slot)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    float w = 0.f;
+    int bad = 0;
+    if (i < d.nx && j < d.ny) {
+        size_t o = (size_t)j * d.pitch + i;
+        if (!isnan(d.f[o])) {
+            const float *H0 = d.Hc + (size_t)j * d.cpitch, *H1 = H0 + d.cpitch;
+            float Hb = 0.25f * ((H0[i] + H1[i]) + (H0[i + 1] + H1[i + 1]));
+            float e = d.eta[o], u = d.hu[o], v = d.hv[o];
+            float h = e + Hb;
+            float ri = rcp(desing(h, d));
+            float c = fsqrt(d.g * fmaxf(h, 0.f));
+            w = fmaxf((fabsf(u * ri) + c) * d.rdx, (fabsf(v * ri) + c) * d.rdy);
+            if (!(isfinite(e) && isfinite(u) && isfinite(v))) bad = 1;
+        }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) w = fmaxf(w, __shfl_xor(w, off, kWave));
+    unsigned long long anybad = __ballot(bad);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicMax(&d.ctrl->wmax[slot], __float_as_uint(w));
+        if (anybad) atomicOr(&d.ctrl->flags, 1u);
+    }
+}
+
+// control block set-up: time, CFL slot cleared, flags cleared
+__global__ void ctrl_reset_kernel(Ctrl *c, double t, int slot)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->t[slot] = t;
+        c->t[slot ^ 1] = t;
+        c->wmax[slot] = 0u;
+        c->wmax[slot ^ 1] = 0u;
+        c->flags = 0u;
+        c->dt_last = 0.f;
+        c->t_end = 0.0;
+    }
+}
+
+__global__ void ctrl_set_t_end_kernel(Ctrl *c, double te)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) c->t_end = te;
+}
+
+// ---------------------------------------------------------------------------
+// float64 diagnostics: per-block partial sums in a fixed order, then one
+// block adds the partials in order (deterministic).
+// ---------------------------------------------------------------------------
+constexpr int kDiagThreads = 256;
+
+__global__ __launch_bounds__(kDiagThreads) void diag_partial_kernel(Dom d)
+{
+    __shared__ double sm[2][kDiagThreads];
+    const int j = blockIdx.x;  // one block per row
+    double m = 0.0, en = 0.0;
+    const double area = d.dx64 * d.dy64;
+    for (int i = threadIdx.x; i < d.nx; i += kDiagThreads) {
+        size_t o = (size_t)j * d.pitch + i;
+        if (isnan(d.f[o])) continue;
+        const float *H0 = d.Hc + (size_t)j * d.cpitch, *H1 = H0 + d.cpitch;
+        double Hb = 0.25 * ((double)H0[i] + (double)H0[i + 1] + (double)H1[i] + (double)H1[i + 1]);
+        double e = d.eta[o], u = d.hu[o], v = d.hv[o];
+        double h = e + Hb;
+        double a = fabs(h), kap = d.kappa64;
+        double hs = fmax(a, fmin(h * h / (2.0 * kap) + 0.5 * kap, kap));
+        hs = h < 0.0 ? -hs : hs;
+        m += h * area;
+        en += (0.5 * (u * u + v * v) / hs + 0.5 * d.g64 * e * e) * area;
+    }
+    sm[0][threadIdx.x] = m;
+    sm[1][threadIdx.x] = en;
+    __syncthreads();
+    for (int s = kDiagThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sm[0][threadIdx.x] += sm[0][threadIdx.x + s];
+            sm[1][threadIdx.x] += sm[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d.partials[2 * j] = sm[0][0];
+        d.partials[2 * j + 1] = sm[1][0];
+    }
+}
+
+__global__ __launch_bounds__(kDiagThreads) void diag_final_kernel(Dom d)
+{
+    __shared__ double sm[2][kDiagThreads];
+    double m = 0.0, en = 0.0;
+    for (int j = threadIdx.x; j < d.ny; j += kDiagThreads) {
+        m += d.partials[2 * j];
+        en += d.partials[2 * j + 1];
+    }
+    sm[0][threadIdx.x] = m;
+    sm[1][threadIdx.x] = en;
+    __syncthreads();
+    for (int s = kDiagThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sm[0][threadIdx.x] += sm[0][threadIdx.x + s];
+            sm[1][threadIdx.x] += sm[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d.ctrl->mass = sm[0][0];
+        d.ctrl->energy = sm[1][0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers (host side)
+// ---------------------------------------------------------------------------
+hipError_t launch_stage(int stage, bool proj, const Dom &d, const Tiling &T, int parity,
+                        double dt_fixed, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    dim3 grid(T.nblocks), block(kWave * kWavesPerBlock);
+    if (ev0) {
+        if (stage == 1) {
+            if (proj) hipExtLaunchKernelGGL(stage_kernel<1, true>, grid, block, 0, s, ev0, ev1, 0, d, T, parity, dt_fixed);
+            else hipExtLaunchKernelGGL(stage_kernel<1, false>, grid, block, 0, s, ev0, ev1, 0, d, T, parity, dt_fixed);
+        } else {
+            if (proj) hipExtLaunchKernelGGL(stage_kernel<2, true>, grid, block, 0, s, ev0, ev1, 0, d, T, parity, dt_fixed);
+            else hipExtLaunchKernelGGL(stage_kernel<2, false>, grid, block, 0, s, ev0, ev1, 0, d, T, parity, dt_fixed);
+        }
+    } else {
+        if (stage == 1) {
+            if (proj) stage_kernel<1, true><<<grid, block, 0, s>>>(d, T, parity, dt_fixed);
+            else stage_kernel<1, false><<<grid, block, 0, s>>>(d, T, parity, dt_fixed);
+        } else {
+            if (proj) stage_kernel<2, true><<<grid, block, 0, s>>>(d, T, parity, dt_fixed);
+            else stage_kernel<2, false><<<grid, block, 0, s>>>(d, T, parity, dt_fixed);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl(const Dom &d, int slot, hipStream_t s)
+{
+    dim3 grid((d.nx + 255) / 256, d.ny), block(256);
+    cfl_kernel<<<grid, block, 0, s>>>(d, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctrl_reset(Ctrl *c, double t, int slot, hipStream_t s)
+{
+    ctrl_reset_kernel<<<1, 64, 0, s>>>(c, t, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_t_end(Ctrl *c, double te, hipStream_t s)
+{
+    ctrl_set_t_end_kernel<<<1, 64, 0, s>>>(c, te);
+    return hipGetLastError();
+}
+
+hipError_t launch_diagnostics(const Dom &d, hipStream_t s)
+{
+    diag_partial_kernel<<<d.ny, kDiagThreads, 0, s>>>(d);
+    diag_final_kernel<<<1, kDiagThreads, 0, s>>>(d);
+    return hipGetLastError();
+}
+
+}  // namespace swe

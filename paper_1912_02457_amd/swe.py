@@ -1,0 +1,244 @@
+"""Python binding of ``lib/libswe_hip.so`` (ctypes).
+
+Argument marshalling only: every step of the scheme runs in the library's HIP
+kernels.  PyTorch provides the device workspace (one ``uint8`` tensor per
+domain) and the HIP stream.  Importing this module without the built library
+raises ImportError -- there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libswe_hip.so")
+
+SWE_OK, SWE_E_ARG, SWE_E_NOMEM, SWE_E_HIP, SWE_E_UNSTABLE, SWE_E_STATE = 0, -1, -2, -3, -4, -5
+BC_WALL, BC_PERIODIC, BC_NESTED = 0, 1, 2
+FRICTION_NONE, FRICTION_LINEAR, FRICTION_QUADRATIC, FRICTION_MANNING = 0, 1, 2, 3
+FORCING_WIND_STRESS, FORCING_BOUNDARY = 0, 1
+
+
+class SweError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"swe error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32),
+        ("dx", C.c_double), ("dy", C.c_double), ("g", C.c_double),
+        ("courant", C.c_double), ("theta", C.c_double), ("kappa", C.c_double),
+        ("bc", C.c_int32 * 4), ("friction", C.c_int32), ("friction_coeff", C.c_double),
+        ("rho_w", C.c_double), ("frs_width", C.c_int32), ("frs_d0", C.c_double),
+        ("north_projection", C.c_int32),
+    ]
+
+
+# exported symbols of include/swe.h and their ctypes signatures
+_VP, _F, _D, _U8 = C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_uint8)
+SIGNATURES = {
+    "swe_workspace_bytes": (C.c_int, [C.POINTER(Params), C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "swe_init_domain": (C.c_int, [C.POINTER(Params), _VP, C.c_size_t, _VP, C.c_int32, C.c_int32,
+                                  _F, _U8, _F, _F, _F, _F, _F, C.POINTER(_VP)]),
+    "swe_set_forcing": (C.c_int, [_VP, C.c_int32, C.c_int32, _D, _F]),
+    "swe_step": (C.c_int, [_VP, C.c_int32]),
+    "swe_step_dt": (C.c_int, [_VP, C.c_int32, _D]),
+    "swe_run_until": (C.c_int, [_VP, C.c_double, C.POINTER(C.c_int64)]),
+    "swe_read_state": (C.c_int, [_VP, _VP, _VP, _VP, _D, _D]),
+    "swe_set_state": (C.c_int, [_VP, _F, _F, _F, C.c_double]),
+    "swe_diagnostics": (C.c_int, [_VP, _D, _D]),
+    "swe_status": (C.c_int, [_VP]),
+    "swe_enable_timing": (C.c_int, [_VP, C.c_int32]),
+    "swe_stage_times": (C.c_int, [_VP, _D, _D, C.POINTER(C.c_int64), C.c_int32]),
+    "swe_destroy": (None, [_VP]),
+    "swe_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1912_02457_amd.build.build() "
+                          "(hipcc, gfx950); there is no CPU fallback")
+    L = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != SWE_OK:
+        raise SweError(rc, load_library().swe_last_error().decode(errors="replace"))
+
+
+def _f32(a, shape) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if a.shape != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {a.shape}")
+    return a
+
+
+def _fp(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_F)
+
+
+def make_params(nx, ny, dx, dy, *, g=9.81, courant=0.45, theta=1.3, kappa=1e-3,
+                bc: Sequence[int] = (BC_WALL,) * 4, friction=FRICTION_NONE, friction_coeff=0.0,
+                rho_w=1025.0, frs_width=10, frs_d0=2.0, north_projection=False) -> Params:
+    p = Params()
+    p.nx, p.ny, p.dx, p.dy, p.g = int(nx), int(ny), float(dx), float(dy), float(g)
+    p.courant, p.theta, p.kappa = float(courant), float(theta), float(kappa)
+    for k in range(4):
+        p.bc[k] = int(bc[k])
+    p.friction, p.friction_coeff = int(friction), float(friction_coeff)
+    p.rho_w, p.frs_width, p.frs_d0 = float(rho_w), int(frs_width), float(frs_d0)
+    p.north_projection = 1 if north_projection else 0
+    return p
+
+
+def workspace_bytes(params: Params, max_wind_times: int = 1, max_bnd_times: int = 0) -> int:
+    n = C.c_size_t()
+    _check(load_library().swe_workspace_bytes(C.byref(params), max_wind_times, max_bnd_times, C.byref(n)))
+    return n.value
+
+
+class Domain:
+    """One simulation domain resident on the GPU."""
+
+    def __init__(self, params: Params, Hc, f, eta, hu, hv, land=None, north=None, *,
+                 max_wind_times: int = 8, max_bnd_times: int = 0, device=None, stream=None):
+        import torch
+        L = load_library()
+        self.params = params
+        nx, ny = params.nx, params.ny
+        self.nx, self.ny = nx, ny
+        self.device = torch.device(device if device is not None else "cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = workspace_bytes(params, max_wind_times, max_bnd_times)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise SweError(SWE_E_ARG, "workspace tensor is not 256-byte aligned")
+        Hc = _f32(Hc, (ny + 1, nx + 1))
+        f = _f32(f, (ny, nx))
+        eta, hu, hv = (_f32(a, (ny, nx)) for a in (eta, hu, hv))
+        north = None if north is None else _f32(north, (ny, nx))
+        land_a = None if land is None else np.ascontiguousarray(np.asarray(land, dtype=np.uint8))
+        if land_a is not None and land_a.shape != (ny, nx):
+            raise ValueError("land mask shape")
+        h = C.c_void_p()
+        _check(L.swe_init_domain(
+            C.byref(params), C.c_void_p(self.workspace.data_ptr()), nbytes,
+            C.c_void_p(self.stream.cuda_stream), max_wind_times, max_bnd_times,
+            _fp(Hc), None if land_a is None else land_a.ctypes.data_as(_U8), _fp(f), _fp(north),
+            _fp(eta), _fp(hu), _fp(hv), C.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_workload(cls, wl, *, north_projection=False, max_wind_times=None, max_bnd_times=None,
+                      device=None, stream=None) -> "Domain":
+        p = make_params(wl.nx, wl.ny, wl.dx, wl.dy, g=wl.g, courant=wl.courant, theta=wl.theta,
+                        kappa=wl.kappa, bc=wl.bc, friction=wl.friction,
+                        friction_coeff=wl.friction_coeff, rho_w=wl.rho_w,
+                        frs_width=wl.frs_width, frs_d0=wl.frs_d0,
+                        north_projection=north_projection)
+        nw = len(wl.wind_t)
+        nb = 0 if wl.bnd is None else len(wl.bnd_t)
+        dom = cls(p, wl.Hc, wl.f, wl.eta, wl.hu, wl.hv, land=wl.land, north=wl.north,
+                  max_wind_times=max(nw, max_wind_times or 1),
+                  max_bnd_times=max(nb, max_bnd_times or 0), device=device, stream=stream)
+        dom.set_wind(wl.wind_t, wl.wind_tau)
+        if wl.bnd is not None:
+            dom.set_boundary(wl.bnd_t, wl.bnd)
+        return dom
+
+    # -- forcing -----------------------------------------------------------
+    def set_wind(self, times, tau):
+        t = np.ascontiguousarray(np.asarray(times, dtype=np.float64))
+        d = _f32(tau, (len(t), 2))
+        _check(load_library().swe_set_forcing(self._h, FORCING_WIND_STRESS, len(t),
+                                              t.ctypes.data_as(_D), _fp(d)))
+
+    def set_boundary(self, times, data):
+        t = np.ascontiguousarray(np.asarray(times, dtype=np.float64))
+        d = _f32(data, (len(t), 3, 2 * self.ny + 2 * self.nx))
+        _check(load_library().swe_set_forcing(self._h, FORCING_BOUNDARY, len(t),
+                                              t.ctypes.data_as(_D), _fp(d)))
+
+    # -- time stepping -----------------------------------------------------
+    def step(self, n: int = 1):
+        _check(load_library().swe_step(self._h, int(n)))
+
+    def step_dt(self, dts):
+        d = np.ascontiguousarray(np.asarray(dts, dtype=np.float64))
+        _check(load_library().swe_step_dt(self._h, len(d), d.ctypes.data_as(_D)))
+
+    def run_until(self, t_end: float) -> int:
+        n = C.c_int64()
+        _check(load_library().swe_run_until(self._h, float(t_end), C.byref(n)))
+        return n.value
+
+    # -- state -------------------------------------------------------------
+    def read_state(self):
+        """Returns (eta, hu, hv, t, dt_next) with host float32 arrays."""
+        e = np.empty((self.ny, self.nx), np.float32)
+        u = np.empty_like(e)
+        v = np.empty_like(e)
+        t, dt = C.c_double(), C.c_double()
+        _check(load_library().swe_read_state(self._h, e.ctypes.data, u.ctypes.data, v.ctypes.data,
+                                             C.byref(t), C.byref(dt)))
+        return e, u, v, t.value, dt.value
+
+    def read_state_into(self, eta, hu, hv):
+        """Copy the state into device tensors of shape (ny, nx), float32."""
+        for a in (eta, hu, hv):
+            if a.dtype.itemsize != 4 or tuple(a.shape) != (self.ny, self.nx) or not a.is_contiguous():
+                raise ValueError("expected contiguous float32 (ny, nx) tensors")
+        t, dt = C.c_double(), C.c_double()
+        _check(load_library().swe_read_state(self._h, eta.data_ptr(), hu.data_ptr(), hv.data_ptr(),
+                                             C.byref(t), C.byref(dt)))
+        return t.value, dt.value
+
+    def set_state(self, eta, hu, hv, t: float = 0.0):
+        e, u, v = (_f32(a, (self.ny, self.nx)) for a in (eta, hu, hv))
+        _check(load_library().swe_set_state(self._h, _fp(e), _fp(u), _fp(v), float(t)))
+
+    def diagnostics(self):
+        m, en = C.c_double(), C.c_double()
+        _check(load_library().swe_diagnostics(self._h, C.byref(m), C.byref(en)))
+        return m.value, en.value
+
+    def status(self) -> int:
+        return load_library().swe_status(self._h)
+
+    def enable_timing(self, on: bool = True):
+        _check(load_library().swe_enable_timing(self._h, 1 if on else 0))
+
+    def stage_times(self, reset: bool = True):
+        a, b, n = C.c_double(), C.c_double(), C.c_int64()
+        _check(load_library().swe_stage_times(self._h, C.byref(a), C.byref(b), C.byref(n), 1 if reset else 0))
+        return a.value, b.value, n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().swe_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

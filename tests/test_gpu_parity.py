@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded float32 inputs, element by element, to 1e-4 relative L2 and
+5e-4 relative Linf per field (eta by its own norm, hu and hv by the momentum
+magnitude), plus self-consistency checks of the GPU path."""
+
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests._parity import assert_parity, parity
+from workloads import (BC_NESTED, BC_PERIODIC, BC_WALL, FRIC_LINEAR, FRIC_MANNING, FRIC_NONE,
+                       FRIC_QUADRATIC, config1, config2, config3, random_small)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    from paper_1912_02457_amd import load_library
+    load_library()
+    return torch
+
+
+def _dom(wl, **kw):
+    from paper_1912_02457_amd import Domain
+    return Domain.from_workload(wl, device="cuda:0", **kw)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_both(wl, nsteps, proj=False):
+    """Oracle with its own CFL dt; GPU once replaying the oracle's dt sequence
+    and once with its own on-device dt."""
+    ref, t_ref, dts, k = O.Oracle(wl).run(nsteps=nsteps)
+    assert k == nsteps
+    d = _dom(wl, north_projection=proj)
+    d.step_dt(dts)
+    rep = d.read_state()
+    d.close()
+    d = _dom(wl, north_projection=proj)
+    d.step(nsteps)
+    own = d.read_state()
+    d.close()
+    return ref, t_ref, rep, own
+
+
+def test_config1_plain_method():
+    """128x128 bump, walls, constant f, 200 steps (the plain-method case)."""
+    wl = config1()
+    _say("config1 200 steps")
+    ref, t_ref, rep, own = run_both(wl, 200)
+    p1 = assert_parity(rep, ref, label="config1 dt-replay")
+    p2 = assert_parity(own, ref, label="config1 own-dt")
+    assert abs(own[3] - t_ref) <= 1e-5 * t_ref
+    _say("config1", p1, p2)
+
+
+CASES = [
+    # name, nx, ny, kwargs
+    ("walls_land", 133, 71, dict(land_frac=0.2, friction=FRIC_LINEAR, friction_coeff=3e-3, wind=(0.1, 0.05))),
+    ("periodic", 64, 48, dict(bc=(BC_PERIODIC,) * 4, friction=FRIC_QUADRATIC, friction_coeff=2e-3)),
+    ("nested_all", 97, 83, dict(bc=(BC_NESTED,) * 4, land_frac=0.1, wind=(-0.05, 0.1))),
+    ("nested_mixed", 61, 130, dict(bc=(BC_NESTED, BC_WALL, BC_PERIODIC, BC_PERIODIC))),
+    ("wet_dry_manning", 120, 90, dict(wet_dry=True, friction=FRIC_MANNING, friction_coeff=0.03, amp=0.5)),
+    ("ragged_small", 5, 3, dict()),
+    ("tiny_2x2", 2, 2, dict(bc=(BC_NESTED, BC_WALL, BC_NESTED, BC_WALL))),
+    ("one_strip_edge", 60, 17, dict(land_frac=0.3)),
+    ("strip_plus_one", 61, 16, dict(bc=(BC_WALL, BC_NESTED, BC_WALL, BC_WALL))),
+    ("tall", 7, 301, dict(bc=(BC_PERIODIC, BC_PERIODIC, BC_NESTED, BC_NESTED), friction=FRIC_LINEAR,
+                          friction_coeff=1e-3)),
+    ("anisotropic", 150, 40, dict(dx=300.0, dy=900.0, land_frac=0.15, wind=(0.2, -0.1))),
+]
+
+
+@pytest.mark.parametrize("name,nx,ny,kw", CASES, ids=[c[0] for c in CASES])
+def test_random_cases(name, nx, ny, kw):
+    wl = random_small(nx, ny, seed=zlib.crc32(name.encode()) % 1000, steps=30, **kw)
+    _say("case", name, nx, ny)
+    ref, t_ref, rep, own = run_both(wl, 30)
+    assert_parity(rep, ref, wl.land, label=f"{name} dt-replay")
+    assert_parity(own, ref, wl.land, label=f"{name} own-dt")
+    if wl.land is not None:
+        lm = wl.land > 0
+        assert np.array_equal(own[0][lm], wl.eta[lm]) and np.array_equal(own[1][lm], wl.hu[lm])
+
+
+def test_north_projection_variant():
+    """The literal north-vector projection kernel agrees with the oracle (which
+    always evaluates the projection) for random north angles."""
+    wl = random_small(90, 70, seed=17, north_random=True, land_frac=0.1, steps=30,
+                      bc=(BC_NESTED, BC_WALL, BC_WALL, BC_NESTED))
+    _say("north projection")
+    ref, t_ref, rep, own = run_both(wl, 30, proj=True)
+    assert_parity(rep, ref, wl.land, label="proj dt-replay")
+    assert_parity(own, ref, wl.land, label="proj own-dt")
+
+
+@pytest.mark.parametrize("which", ["config2", "config3"])
+def test_full_size_first_steps(which):
+    """Full-size NorKyst-shaped and wet-dry domains: 3 steps, the launch
+    configuration the benchmark times, every cell compared."""
+    wl = config2() if which == "config2" else config3()
+    _say("full size", which, wl.nx, wl.ny)
+    ref, t_ref, dts, k = O.Oracle(wl).run(nsteps=3)
+    d = _dom(wl)
+    d.step_dt(dts)
+    rep = d.read_state()
+    d.close()
+    d = _dom(wl)
+    d.step(3)
+    own = d.read_state()
+    d.close()
+    p1 = assert_parity(rep, ref, wl.land, label=f"{which} dt-replay")
+    p2 = assert_parity(own, ref, wl.land, label=f"{which} own-dt")
+    _say(which, p1, p2)
+
+
+def test_config3_runs_dry_front_stays_sane():
+    """500 steps of the wet-dry beach: no NaN, depth non-negative up to the
+    dry tolerance scale, incoming wave entered."""
+    wl = config3()
+    d = _dom(wl)
+    d.step(500)
+    e, u, v, t, dt = d.read_state()
+    d.close()
+    Hc = wl.Hc.astype(np.float64)
+    hb = e + 0.25 * (Hc[:-1, :-1] + Hc[:-1, 1:] + Hc[1:, :-1] + Hc[1:, 1:])
+    assert np.all(np.isfinite(e)) and hb.min() > -1e-2
+    assert np.abs(e[:, :50]).max() > 0.05
+
+
+def test_repeatable_and_graph_equals_direct():
+    """Bitwise repeatability, and the HIP-graph path (chunks of 16 steps)
+    equals direct launches bit for bit."""
+    wl = random_small(200, 150, seed=4, land_frac=0.2, bc=(BC_NESTED, BC_WALL, BC_NESTED, BC_WALL),
+                      friction=FRIC_MANNING, friction_coeff=0.03)
+    outs = []
+    for timing in (False, False, True):
+        d = _dom(wl)
+        if timing:
+            d.enable_timing(True)  # timing mode launches kernels one by one
+        d.step(40)
+        outs.append(d.read_state())
+        d.close()
+    for k in range(3):
+        assert np.array_equal(outs[0][k], outs[1][k])
+        assert np.array_equal(outs[0][k], outs[2][k])
+    assert outs[0][3] == outs[1][3] == outs[2][3]
+
+
+def test_checkpoint_resume_bitwise():
+    wl = random_small(100, 70, seed=8, land_frac=0.1, friction=FRIC_LINEAR, friction_coeff=2e-3,
+                      wind=(0.1, 0.0))
+    d = _dom(wl)
+    d.step(25)
+    full = d.read_state()
+    d.close()
+    d = _dom(wl)
+    d.step(10)
+    e, u, v, t, _ = d.read_state()
+    d.close()
+    d2 = _dom(wl)
+    d2.set_state(e, u, v, t)
+    d2.step(15)
+    res = d2.read_state()
+    d2.close()
+    for k in range(3):
+        assert np.array_equal(full[k], res[k])
+    assert full[3] == res[3]
+
+
+def test_run_until_hits_t_end_and_matches_oracle():
+    wl = random_small(80, 64, seed=12, bc=(BC_NESTED, BC_NESTED, BC_WALL, BC_WALL))
+    t_end = 157.25
+    ref, t_ref, dts, k = O.Oracle(wl).run(nsteps=100000, t_end=t_end)
+    d = _dom(wl)
+    n = d.run_until(t_end)
+    st = d.read_state()
+    d.close()
+    assert st[3] == t_end and t_ref == t_end
+    assert n == k
+    assert_parity(st, ref, wl.land, label="run_until")
+
+
+def test_diagnostics_match_oracle():
+    wl = random_small(90, 77, seed=6, land_frac=0.25)
+    o = O.Oracle(wl)
+    m0, e0 = o.diagnostics(o.initial_state())
+    d = _dom(wl)
+    m, e = d.diagnostics()
+    assert m == pytest.approx(m0, rel=1e-12)
+    assert e == pytest.approx(e0, rel=1e-10)
+    d.step(50)
+    m1, e1 = d.diagnostics()
+    d.close()
+    assert abs(m1 - m0) / m0 < 1e-6  # closed basin: mass conserved to float32 state rounding
+
+
+def test_unstable_flag_raised():
+    """An overflowing momentum field (finite input) makes the state non-finite;
+    the device flag turns into SWE_E_UNSTABLE on the next synchronising call."""
+    from paper_1912_02457_amd import SweError
+    wl = random_small(64, 32, seed=3)
+    wl = wl.copy(hu=np.full_like(wl.hu, 3e38))
+    d = _dom(wl)
+    d.step(3)
+    with pytest.raises(SweError) as ei:
+        d.read_state()
+    assert ei.value.code == -4
+    d.close()
+
+
+def test_lake_at_rest_gpu():
+    """Float32 GPU: a lake at rest over random bathymetry with land, f and
+    nested sides holding the rest state stays at rest to float32 rounding."""
+    wl = random_small(150, 100, seed=2, land_frac=0.2, bc=(BC_NESTED, BC_WALL, BC_WALL, BC_NESTED),
+                      depth=(20.0, 3000.0))
+    wl = wl.copy(eta=np.zeros_like(wl.eta), hu=np.zeros_like(wl.hu), hv=np.zeros_like(wl.hv),
+                 bnd=np.zeros_like(wl.bnd), wind_tau=np.zeros_like(wl.wind_tau))
+    d = _dom(wl)
+    d.step(200)
+    e, u, v, t, _ = d.read_state()
+    d.close()
+    assert np.abs(e).max() == 0.0
+    assert np.abs(u).max() == 0.0 and np.abs(v).max() == 0.0

@@ -87,6 +87,7 @@ def main():
     land_cells = int(np.count_nonzero(wl.land)) if wl.land is not None else 0
     wet_cells = cells - land_cells
     dom = Domain.from_workload(wl, device="cuda:0")
+    rows_per_wave, waves = dom.tiling()
 
     dom.step(a.warmup)
     torch.cuda.synchronize()
@@ -145,6 +146,7 @@ def main():
             "nx": wl.nx, "ny": wl.ny, "dx_m": wl.dx, "cells": cells, "land_fraction": land_cells / cells,
             "boundaries": "nested (M2 tide, hourly snapshots) on all sides", "friction": "linear r=3e-3 m/s",
             "wind_stress_Nm2": 0.1, "courant": wl.courant, "dt_s": dt_next,
+            "rows_per_wave": rows_per_wave, "waves_per_stage": waves,
         },
         "roofline": {
             "bound": "hbm",

@@ -153,6 +153,14 @@ int swe_diagnostics(swe_domain *d, double *mass, double *energy);
  * Synchronises. */
 int swe_status(swe_domain *d);
 
+/* Work decomposition of the stage kernels: each wavefront updates a strip of
+ * 60 columns over rows_per_wave rows (0 = the built-in choice, which fills
+ * the GPU's wave slots in whole rounds).  Used by the autotuner; the results
+ * do not depend on it (bitwise).  swe_get_tiling reports the current rows per
+ * wave and the number of wavefronts per stage launch. */
+int swe_set_tiling(swe_domain *d, int32_t rows_per_wave);
+int swe_get_tiling(swe_domain *d, int32_t *rows_per_wave, int32_t *waves);
+
 /* Average device time per launch of each stage kernel (milliseconds) over
  * the launches issued since the last call with reset != 0, measured with HIP
  * events recorded around every stage launch on the domain's stream while

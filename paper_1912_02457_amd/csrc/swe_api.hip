@@ -139,6 +139,7 @@ struct swe_domain {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     int64_t timed_steps = 0;
+    int cus = 256;
 };
 
 namespace {
@@ -330,7 +331,12 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
     D.nw = 0; D.wind_t = (const double *)(w + L.wind_t); D.wind = (const float *)(w + L.wind);
     D.ctrl = (Ctrl *)(w + L.ctrl);
     D.partials = (double *)(w + L.partials);
-    d->T = make_tiling(nx, ny, 16);
+    {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        d->cus = cus > 0 ? cus : 256;
+    }
+    d->T = make_tiling(nx, ny, pick_rows_per_wave(nx, ny, d->cus, 4));
 
     hipStream_t s = d->stream;
     int r = SWE_OK;
@@ -343,7 +349,7 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
     build_ghost_table(*p, f, fg);
     build_ghost_table(*p, theta, ng);
     for (int k = 0; k < kMaxFrs; ++k) alpha[k] = (float)(1.0 - std::tanh((double)k / p->frs_d0));
-    Ctrl c0{};
+    static const Ctrl c0{};
     if ((r = upload_pitched(d, L.eta, eta, nx, ny, D.pitch, s)) ||
         (r = upload_pitched(d, L.hu, hu, nx, ny, D.pitch, s)) ||
         (r = upload_pitched(d, L.hv, hv, nx, ny, D.pitch, s)) ||
@@ -470,9 +476,7 @@ int swe_run_until(swe_domain *d, double t_end, int64_t *steps_taken)
             t = c.t[d->parity];
             if (c.flags) break;
             if (t >= t_end) break;
-            float wm;
-            uint32_t wb = c.wmax[d->parity];
-            std::memcpy(&wm, &wb, sizeof(wm));
+            float wm = ctrl_wmax(c, d->parity);
             double dt = wm > 0 ? (double)(d->dom.courant_q / wm) : 1.0;
             double est = (t_end - t) / dt;
             int n = (int)std::min<double>(chunk_max, std::max<double>(kGraphChunk, std::ceil(est * 1.05) + 1));
@@ -503,9 +507,7 @@ int swe_read_state(swe_domain *d, float *eta, float *hu, float *hv, double *t, d
     if (rc) return rc;
     if (t) *t = c.t[d->parity];
     if (dt_next) {
-        float wm;
-        uint32_t wb = c.wmax[d->parity];
-        std::memcpy(&wm, &wb, sizeof(wm));
+        float wm = ctrl_wmax(c, d->parity);
         *dt_next = wm > 0 ? (double)(d->dom.courant_q / wm) : INFINITY;
     }
     if (c.flags) return fail(SWE_E_UNSTABLE, "non-finite state");
@@ -548,6 +550,27 @@ int swe_status(swe_domain *d)
     int rc = read_ctrl(d, &c);
     if (rc) return rc;
     return c.flags ? fail(SWE_E_UNSTABLE, "non-finite state") : SWE_OK;
+}
+
+int swe_set_tiling(swe_domain *d, int32_t rows_per_wave)
+{
+    if (!d) return fail(SWE_E_ARG, "domain is NULL");
+    if (rows_per_wave < 0 || rows_per_wave > 4096) return fail(SWE_E_ARG, "rows_per_wave out of range");
+    int by = rows_per_wave ? rows_per_wave : pick_rows_per_wave(d->p.nx, d->p.ny, d->cus, 4);
+    d->T = make_tiling(d->p.nx, d->p.ny, by);
+    for (auto &kv : d->graphs) hipGraphExecDestroy(kv.second);
+    for (auto g : d->graph_objs) hipGraphDestroy(g);
+    d->graphs.clear();
+    d->graph_objs.clear();
+    return SWE_OK;
+}
+
+int swe_get_tiling(swe_domain *d, int32_t *rows_per_wave, int32_t *waves)
+{
+    if (!d) return fail(SWE_E_ARG, "domain is NULL");
+    if (rows_per_wave) *rows_per_wave = d->T.by;
+    if (waves) *waves = d->T.ntiles;
+    return SWE_OK;
 }
 
 int swe_enable_timing(swe_domain *d, int32_t on)

@@ -23,19 +23,37 @@ constexpr int kStrip = kWave - 2 * kHalo;  // output columns per wave
 constexpr int kWavesPerBlock = 4;
 constexpr int kMaxFrs = 32;
 
+// The CFL maximum is accumulated with atomicMax into kCflSlots words, each on
+// its own 128-byte line and picked by tile index, so that thousands of
+// wavefronts do not serialise on one address; readers take the max of the
+// slots (one per lane of a wavefront).
+constexpr int kCflSlots = 64;
+constexpr int kCflStride = 32;  // uint32 words between slots (128 B)
+
 // Control block; the time and the CFL accumulator are double-buffered by
 // step parity so that both stage kernels of a step read the same values
 // while the next step's slots are being produced.
 struct Ctrl {
     double t[2];         // time at the start of the step of each parity
-    uint32_t wmax[2];    // max over non-land cells of max((|u|+c)/dx, (|v|+c)/dy), float bits
     uint32_t flags;      // bit 0: non-finite state produced
     float dt_last;       // dt of the last step taken
     int64_t steps;       // steps taken (no-op steps past t_end excluded)
     double t_end;        // > 0: clamp steps to end exactly at t_end, skip steps after it
     double mass, energy; // results of the diagnostics reduction
-    double pad[2];
+    double pad[9];
+    // max over non-land cells of max((|u|+c)/dx, (|v|+c)/dy) as float bits, per parity
+    uint32_t wslot[2][kCflSlots][kCflStride];
 };
+
+// host-side maximum over the slots of one parity
+inline float ctrl_wmax(const Ctrl &c, int parity)
+{
+    uint32_t m = 0;
+    for (int k = 0; k < kCflSlots; ++k) m = c.wslot[parity][k][0] > m ? c.wslot[parity][k][0] : m;
+    float f;
+    __builtin_memcpy(&f, &m, sizeof(f));
+    return f;
+}
 
 // Everything a stage kernel needs, passed by value.
 struct Dom {
@@ -70,6 +88,24 @@ struct Tiling {
     int ntiles;   // nstrips * nrb
     int nblocks;  // ceil(ntiles / kWavesPerBlock)
 };
+
+// Rows per wave for a domain: fill the wave slots of the device (waves_per_simd
+// resident per SIMD, 4 SIMDs per CU) in whole rounds while keeping the 2-row
+// halo of each tile (about 2.5 rows of extra work) small.
+inline int pick_rows_per_wave(int nx, int ny, int cus, int waves_per_simd)
+{
+    const long slots = (long)cus * 4 * waves_per_simd;
+    const long nstrips = (nx + kStrip - 1) / kStrip;
+    int best = 16;
+    double best_cost = 1e300;
+    for (int by = 4; by <= 256; by += (by < 16 ? 1 : (by < 64 ? 4 : 16))) {
+        long waves = nstrips * ((ny + by - 1) / by);
+        long rounds = (waves + slots - 1) / slots;
+        double cost = (double)rounds * (by + 2.5);
+        if (cost < best_cost - 1e-9) { best_cost = cost; best = by; }
+    }
+    return best;
+}
 
 inline Tiling make_tiling(int nx, int ny, int by)
 {

@@ -36,12 +36,16 @@ namespace swe {
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// value held by lane-1 / lane+1 (edge lanes get an unspecified value; they
-// are halo lanes whose results are never stored)
-__device__ __forceinline__ float from_left(float v) { return __shfl_up(v, 1, kWave); }
-__device__ __forceinline__ float from_right(float v) { return __shfl_down(v, 1, kWave); }
-__device__ __forceinline__ int from_left(int v) { return __shfl_up(v, 1, kWave); }
-__device__ __forceinline__ int from_right(int v) { return __shfl_down(v, 1, kWave); }
+// Value held by lane-1 / lane+1 through a whole-wave DPP shift (wave_shr:1
+// and wave_shl:1 of the GFX9 DPP controls; a VALU operand modifier, no LDS
+// round trip).  Lane 0 / lane 63 receive 0; they are halo lanes whose results
+// are never stored.
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
+__device__ __forceinline__ int from_left(int v) { return __builtin_amdgcn_update_dpp(0, v, kDppWaveShr1, 0xF, 0xF, false); }
+__device__ __forceinline__ int from_right(int v) { return __builtin_amdgcn_update_dpp(0, v, kDppWaveShl1, 0xF, 0xF, false); }
+__device__ __forceinline__ float from_left(float v) { return __int_as_float(from_left(__float_as_int(v))); }
+__device__ __forceinline__ float from_right(float v) { return __int_as_float(from_right(__float_as_int(v))); }
 
 // eq. desing_ours
 __device__ __forceinline__ float desing(float h, const Dom &d)
@@ -68,6 +72,21 @@ __device__ __forceinline__ void time_weights(int n, const double *ts, double tau
     while (a < n - 2 && ts[a + 1] <= tau) ++a;
     k = a;
     s = (tau - ts[a]) / (ts[a + 1] - ts[a]);
+}
+
+// wave-wide maximum of a float (every lane gets the result)
+__device__ __forceinline__ float wave_max(float v)
+{
+    for (int off = kWave / 2; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// CFL accumulator of one parity: maximum over the slots (all lanes get it)
+__device__ __forceinline__ uint32_t read_wmax(const Ctrl *c, int parity, int lane)
+{
+    uint32_t v = c->wslot[parity][lane & (kCflSlots - 1)][0];
+    for (int off = kWave / 2; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, kWave));
+    return v;
 }
 
 __device__ __forceinline__ float ext_value(const Dom &d, int k, double s, int fld, int idx)
@@ -158,6 +177,10 @@ struct F3 { float e, p, q; };
 // and a right state; p is the momentum normal to the face, q the transverse
 // one.  Desingularised velocities, face momenta recomputed as h u, wave
 // speeds a+ >= 0 >= a-, transverse momentum upwinded on the mass flux.
+// Written with the weights alpha = a+/(a+ - a-), 1 - alpha and
+// gamma = a+ a-/(a+ - a-); when a+ = a- = 0 (both sides dry and at rest)
+// alpha = 1/2, gamma = 0 give the average of the two physical fluxes.  No
+// branches, so the flux of a face can be interleaved with other work.
 // The pressure uses the perturbation form (see the file header).
 __device__ __forceinline__ F3 cu_flux(float eL, float pL0, float qL0, float eR, float pR0, float qR0,
                                       float Hf, const Dom &d)
@@ -174,17 +197,15 @@ __device__ __forceinline__ F3 cu_flux(float eL, float pL0, float qL0, float eR, 
     float PL = 0.5f * d.g * (eL + Hn) * (eL + Hs2), PR = 0.5f * d.g * (eR + Hn) * (eR + Hs2);
     float FL = fmaf(pL, uL, PL), FR = fmaf(pR, uR, PR);
     float den = ap - am;
+    bool wet = den > 0.f;
+    float w = wet ? rcp(den) : 0.f;
+    float al = wet ? ap * w : 0.5f;
+    float be = 1.f - al;
+    float ga = ap * am * w;
     F3 r;
-    if (den > 0.f) {
-        float w = rcp(den), aw = ap * am * w;
-        r.e = (ap * pL - am * pR) * w + aw * (eR - eL);
-        r.p = (ap * FL - am * FR) * w + aw * (pR - pL);
-        r.q = r.e * (r.e >= 0.f ? vL : vR);
-    } else {
-        r.e = 0.5f * (pL + pR);
-        r.p = 0.5f * (FL + FR);
-        r.q = 0.5f * (pL * vL + pR * vR);
-    }
+    r.e = fmaf(al, pL, fmaf(be, pR, ga * (eR - eL)));
+    r.p = fmaf(al, FL, fmaf(be, FR, ga * (pR - pL)));
+    r.q = r.e * (r.e >= 0.f ? vL : vR);
     return r;
 }
 
@@ -211,40 +232,45 @@ __device__ __forceinline__ float bathy_source(float eta, float eE, float eW, flo
     return (HE >= 0.f && HW >= 0.f) ? deep : gen;
 }
 
-// bed shear stress coefficient S >= 0, the source being -S (hu, hv)
-__device__ __forceinline__ float friction_coeff(const Dom &d, float h, float hu, float hv)
+// bed shear stress coefficient S >= 0, the source being -S (hu, hv), from the
+// cell's reciprocal desingularised depth ri = 1/h*
+__device__ __forceinline__ float friction_coeff(const Dom &d, float ri, float hu, float hv)
 {
     if (d.friction == FR_NONE) return 0.f;
-    float a = fabsf(desing(h, d));
-    float ra = rcp(a);
+    float ra = fabsf(ri);
     if (d.friction == FR_LINEAR) return d.fric_c * ra;
     float speed = fsqrt(hu * hu + hv * hv) * ra;
     if (d.friction == FR_QUADRATIC) return d.fric_c * speed * ra * ra;
-    // Manning: g n^2 |u| / a^(4/3)
-    float a43 = __builtin_amdgcn_exp2f((4.0f / 3.0f) * __builtin_amdgcn_logf(a));
-    return d.fric_c * speed * rcp(a43);
+    // Manning: g n^2 |u| / a^(4/3) = g n^2 |u| ra^(4/3)
+    float ra43 = __builtin_amdgcn_exp2f((4.0f / 3.0f) * __builtin_amdgcn_logf(ra));
+    return d.fric_c * speed * ra43;
 }
 
-// One row of cells of the sliding window (per lane: column i).
+// One row of the sliding window (per lane: column i).
 struct Row {
-    float e, u, v, f;    // state (ghost-resolved) and Coriolis parameter
-    float cx, cy;        // Coriolis terms of the reconstruction (f v, -f u)
-    float cn0, cn1;      // corner depths at (i, r+1), (i+1, r+1)
+    float e, u, v, f;      // state (ghost-resolved) and Coriolis parameter (NaN: land)
+    float cx, cy;          // Coriolis terms of the reconstruction (f v, -f u)
     float Hw, He, Hs, Hn, Hb;
+    float ri;              // 1 / h* of the cell
     int land;
-    float dmL, dmU, dmV; // y backward differences (this row minus the row below)
+    float dmL, dmU, dmV;   // y backward differences (this row minus the row below)
+    float eN, eS, uN, vN;  // north/south face values once the row was the middle row
 };
 
+// face depths, mean depth, land flag and Coriolis terms of a row from its
+// four corner depths (south corners cs*, north corners cn*)
 template <bool PROJ>
-__device__ __forceinline__ void cell_terms(Row &R, float cs0, float cs1, float th, const Dom &d)
+__device__ __forceinline__ void row_terms(Row &R, float cs0, float cs1, float cn0, float cn1, float th,
+                                          const Dom &d)
 {
-    R.Hw = 0.5f * (cs0 + R.cn0);
-    R.He = 0.5f * (cs1 + R.cn1);
+    R.Hw = 0.5f * (cs0 + cn0);
+    R.He = 0.5f * (cs1 + cn1);
     R.Hs = 0.5f * (cs0 + cs1);
-    R.Hn = 0.5f * (R.cn0 + R.cn1);
-    R.Hb = 0.25f * ((cs0 + R.cn0) + (cs1 + R.cn1));
+    R.Hn = 0.5f * (cn0 + cn1);
+    R.Hb = 0.25f * ((cs0 + cn0) + (cs1 + cn1));
     float h = R.e + R.Hb;
     float ri = rcp(desing(h, d));
+    R.ri = ri;
     float uu = R.u * ri, vv = R.v * ri;
     R.land = isnan(R.f) ? 1 : 0;
     if (PROJ) {
@@ -255,6 +281,289 @@ __device__ __forceinline__ void cell_terms(Row &R, float cs0, float cs1, float t
     } else {
         R.cx = R.f * vv;
         R.cy = -R.f * uu;
+    }
+}
+
+// backward differences along y of row C against the row B below it; the
+// K-type difference of eq. Kbackwards in its y form (L = g(eta + U))
+__device__ __forceinline__ void y_diff(Row &C, const Row &B, const Dom &d)
+{
+    C.dmL = C.e - B.e - d.ky * (B.cy + C.cy);
+    C.dmU = C.u - B.u;
+    C.dmV = C.v - B.v;
+}
+
+// limited y-slopes and N/S face values of row B (eq. hE in its N/S form with
+// the wet-dry fix of eq. KxE_adjust); stores the N values and eS in B and
+// returns the S momenta for the face below B
+__device__ __forceinline__ void y_faces(Row &B, const Row &C, int landA, const Dom &d, float &uS, float &vS)
+{
+    const float th = d.theta;
+    float sL = limited(B.dmL, C.dmL, th);
+    float sU = limited(B.dmU, C.dmU, th);
+    float sV = limited(B.dmV, C.dmV, th);
+    if (landA || C.land) sL = sU = sV = 0.f;  // first order next to land
+    float rho = 0.5f * sL + d.ky * B.cy;
+    float eN = B.e + rho, eS = B.e - rho;
+    if (eN + B.Hn < 0.f) { eN = -B.Hn; eS = 2.f * B.e - eN; }
+    if (eS + B.Hs < 0.f) { eS = -B.Hs; eN = 2.f * B.e - eS; }
+    B.eN = eN;
+    B.eS = eS;
+    B.uN = B.u + 0.5f * sU;
+    B.vN = B.v + 0.5f * sV;
+    uS = B.u - 0.5f * sU;
+    vS = B.v - 0.5f * sV;
+}
+
+// flux through the face between row A (below, its N values) and row B
+// (above, its S values): normal momentum hv, transverse hu
+__device__ __forceinline__ F3 y_flux(const Row &A, const Row &B, float uS, float vS, const Dom &d)
+{
+    return face_flux(A.eN, A.vN, A.uN, B.eS, vS, uS, A.land != 0, B.land != 0, B.Hs, d);
+}
+
+struct TileCtx {
+    int i, o;        // column of this lane, output row
+    bool out_lane;   // lane owns an output cell
+    float dt, wx, wy;
+    int bk;          // boundary snapshot interval and weight at the stage time
+    double bs;
+};
+
+// x-direction reconstruction and flux of the output row A, the update of
+// eq. rk2_semiimp and (stage 2) the flow relaxation and CFL reduction.
+// Every lane takes part in the cross-lane exchanges; only output lanes store.
+template <int STAGE, bool PROJ, bool FRS>
+__device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 &Gn, const TileCtx &c,
+                                           float e0, float u0, float v0, const Dom &d, float &wmax_loc, int &bad)
+{
+    const float th = d.theta;
+    float eL = from_left(A.e), cxL = from_left(A.cx);
+    float uL = from_left(A.u), vL = from_left(A.v);
+    int landL = from_left(A.land), landR = from_right(A.land);
+    float dmK = A.e - eL - d.kx * (cxL + A.cx);
+    float dmU = A.u - uL, dmV = A.v - vL;
+    float sK = limited(dmK, from_right(dmK), th);
+    float sUx = limited(dmU, from_right(dmU), th);
+    float sVx = limited(dmV, from_right(dmV), th);
+    if (landL || landR) sK = sUx = sVx = 0.f;
+    float rx = 0.5f * sK + d.kx * A.cx;
+    float eE = A.e + rx, eW = A.e - rx;
+    if (eE + A.He < 0.f) { eE = -A.He; eW = 2.f * A.e - eE; }
+    if (eW + A.Hw < 0.f) { eW = -A.Hw; eE = 2.f * A.e - eW; }
+    float uE = A.u + 0.5f * sUx, uW = A.u - 0.5f * sUx;
+    float vE = A.v + 0.5f * sVx, vW = A.v - 0.5f * sVx;
+    F3 Fe = face_flux(eE, uE, vE, from_right(eW), from_right(uW), from_right(vW), A.land != 0, landR != 0,
+                      A.He, d);
+    float Fwe = from_left(Fe.e), Fwp = from_left(Fe.p), Fwq = from_left(Fe.q);
+    // every lane computes; only output lanes over water store (no early exit,
+    // so the x and y work of neighbouring rows can be interleaved)
+    const bool store = c.out_lane && !A.land;
+
+    float Cx, Cy;
+    if (PROJ) {
+        float ang = store ? d.north[(size_t)c.o * d.pitch + c.i] : 0.f;
+        float cc = __cosf(ang), ss = __sinf(ang);
+        float hue = cc * A.u - ss * A.v, hvn = ss * A.u + cc * A.v;
+        Cx = A.f * (cc * hvn - ss * hue);
+        Cy = A.f * (-ss * hvn - cc * hue);
+    } else {
+        Cx = A.f * A.v;
+        Cy = -A.f * A.u;
+    }
+    float Me = -(Fe.e - Fwe) * d.rdx - (Gn.e - Gs.e) * d.rdy;
+    float Mu = -(Fe.p - Fwp) * d.rdx - (Gn.q - Gs.q) * d.rdy + bathy_source(A.e, eE, eW, A.He, A.Hw, d) * d.rdx +
+               Cx + c.wx;
+    float Mv = -(Fe.q - Fwq) * d.rdx - (Gn.p - Gs.p) * d.rdy +
+               bathy_source(A.e, A.eN, A.eS, A.Hn, A.Hs, d) * d.rdy + Cy + c.wy;
+    const size_t oo = (size_t)c.o * d.pitch + c.i;
+    const float dt = c.dt;
+    float S = friction_coeff(d, A.ri, A.u, A.v);
+    if (STAGE == 1) {
+        float den = rcp(1.f + dt * S);
+        float en = A.e + dt * Me;
+        float un = (A.u + dt * Mu) * den;
+        float vn = (A.v + dt * Mv) * den;
+        if (store) {
+            d.eta1[oo] = en;
+            d.hu1[oo] = un;
+            d.hv1[oo] = vn;
+        }
+    } else {
+        float den = rcp(1.f + 0.5f * dt * S);
+        float en = 0.5f * (e0 + (A.e + dt * Me));
+        float un = 0.5f * (u0 + (A.u + dt * Mu)) * den;
+        float vn = 0.5f * (v0 + (A.v + dt * Mv)) * den;
+        if (FRS && store && d.frs_w > 0) {
+            // eq. frs: nearest nested side within the zone, ties W, E, S, N
+            const int nx = d.nx, ny = d.ny, i = c.i, o = c.o;
+            int dist[4] = {i, nx - 1 - i, o, ny - 1 - o};
+            int idxs[4] = {o, ny + o, 2 * ny + i, 2 * ny + nx + i};
+            int best = -1, dd = 0;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                if (d.bc[s] == BC_NESTED && (best < 0 || dist[s] < dd)) { best = s; dd = dist[s]; }
+            if (best >= 0 && dd < d.frs_w) {
+                int idx = best == 0 ? idxs[0] : best == 1 ? idxs[1] : best == 2 ? idxs[2] : idxs[3];
+                float al = d.frs_alpha[dd];
+                en = (1.f - al) * en + al * ext_value(d, c.bk, c.bs, 0, idx);
+                un = (1.f - al) * un + al * ext_value(d, c.bk, c.bs, 1, idx);
+                vn = (1.f - al) * vn + al * ext_value(d, c.bk, c.bs, 2, idx);
+            }
+        }
+        if (store) {
+            d.eta[oo] = en;
+            d.hu[oo] = un;
+            d.hv[oo] = vn;
+        }
+        // eq. cfl on the new state
+        float h = en + A.Hb;
+        float ri = rcp(desing(h, d));
+        float cw = fsqrt(d.g * fmaxf(h, 0.f));
+        float w = fmaxf((fabsf(un * ri) + cw) * d.rdx, (fabsf(vn * ri) + cw) * d.rdy);
+        wmax_loc = store ? fmaxf(wmax_loc, w) : wmax_loc;
+        bad |= (store && !(isfinite(en) && isfinite(un) && isfinite(vn))) ? 1 : 0;
+    }
+}
+
+// ---- interior tiles: every cell of the tile and its 2-cell halo lies inside
+// the domain and outside any relaxation zone.  Plain 32-bit-offset loads, the
+// next row prefetched while the current one is processed, the window rotated
+// by unrolling (no register moves, no per-row branches). -----------------------
+struct RawRow { float e, u, v, f, cn0, cn1, th; };
+
+template <bool PROJ>
+__device__ __forceinline__ RawRow load_raw(const Dom &d, const float *__restrict__ E, const float *__restrict__ U,
+                                           const float *__restrict__ V, uint32_t off, uint32_t cof)
+{
+    RawRow r;
+    r.e = E[off];
+    r.u = U[off];
+    r.v = V[off];
+    r.f = d.f[off];
+    r.cn0 = d.Hc[cof];
+    r.cn1 = d.Hc[cof + 1];
+    r.th = PROJ ? d.north[off] : 0.f;
+    return r;
+}
+
+template <int STAGE, bool PROJ>
+__device__ __forceinline__ void tile_interior(const Dom &d, TileCtx c, int y0, int y1, float &wmax_loc, int &bad)
+{
+    const float *__restrict__ E = STAGE == 1 ? d.eta : d.eta1;
+    const float *__restrict__ U = STAGE == 1 ? d.hu : d.hu1;
+    const float *__restrict__ V = STAGE == 1 ? d.hv : d.hv1;
+    const uint32_t pitch = d.pitch, cpitch = d.cpitch;
+    uint32_t off = (uint32_t)(y0 - 2) * pitch + c.i;   // cell row to load next
+    uint32_t cof = (uint32_t)(y0 - 1) * cpitch + c.i;  // its north corner row
+    float cs0 = d.Hc[cof - cpitch], cs1 = d.Hc[cof - cpitch + 1];
+    RawRow nxt = load_raw<PROJ>(d, E, U, V, off, cof);
+    const int klast = y1 + 1;
+
+    auto load = [&](Row &C, int k) {
+        RawRow cur = nxt;
+        if (k < klast) nxt = load_raw<PROJ>(d, E, U, V, off + pitch, cof + cpitch);
+        off += pitch;
+        cof += cpitch;
+        C.e = cur.e; C.u = cur.u; C.v = cur.v; C.f = cur.f;
+        row_terms<PROJ>(C, cs0, cs1, cur.cn0, cur.cn1, cur.th, d);
+        cs0 = cur.cn0;
+        cs1 = cur.cn1;
+    };
+
+    Row R0, R1, R2;
+    float uS, vS;
+    load(R0, y0 - 2);
+    load(R1, y0 - 1);
+    y_diff(R1, R0, d);
+    load(R2, y0);
+    y_diff(R2, R1, d);
+    y_faces(R1, R2, R0.land, d, uS, vS);
+    load(R0, y0 + 1);
+    y_diff(R0, R2, d);
+    y_faces(R2, R0, R1.land, d, uS, vS);
+    F3 Gs = y_flux(R1, R2, uS, vS, d);
+
+    // steady state: A = row k-2 (output), B = row k-1, C = row k
+    auto step = [&](Row &A, Row &B, Row &C, int k) {
+        float e0 = 0.f, u0 = 0.f, v0 = 0.f;
+        const uint32_t oq = off - 2 * pitch;  // output row k-2 (off points at row k)
+        if (STAGE == 2) { e0 = d.eta[oq]; u0 = d.hu[oq]; v0 = d.hv[oq]; }
+        load(C, k);
+        y_diff(C, B, d);
+        float us, vs;
+        y_faces(B, C, A.land, d, us, vs);
+        F3 Gn = y_flux(A, B, us, vs, d);
+        c.o = k - 2;
+        finish_row<STAGE, PROJ, false>(A, Gs, Gn, c, e0, u0, v0, d, wmax_loc, bad);
+        Gs = Gn;
+    };
+    for (int k = y0 + 2;;) {
+        step(R2, R0, R1, k);
+        if (++k > klast) break;
+        step(R0, R1, R2, k);
+        if (++k > klast) break;
+        step(R1, R2, R0, k);
+        if (++k > klast) break;
+    }
+}
+
+// ---- edge tiles: ghost cells from the boundary kinds, relaxation zone -------
+template <int STAGE, bool PROJ>
+__device__ __forceinline__ void tile_edge(const Dom &d, TileCtx c, int y0, int y1, int lane, float &wmax_loc, int &bad)
+{
+    const float *__restrict__ E = STAGE == 1 ? d.eta : d.eta1;
+    const float *__restrict__ U = STAGE == 1 ? d.hu : d.hu1;
+    const float *__restrict__ V = STAGE == 1 ? d.hv : d.hv1;
+    const int nx = d.nx, ny = d.ny;
+    const int il = min(c.i, nx + 1);  // lanes right of the east ghosts load a ghost column
+    const bool xin = il >= 0 && il < nx;
+    (void)lane;
+
+    // Lanes in a ghost column only ever contribute rows inside [0, ny); their
+    // rows outside (diagonal ghosts) are clamped to stay in bounds and are
+    // never used.  Corner rows are clamped separately so that row 0 still
+    // sees corner row 0 as its south side.
+    float cs0, cs1;
+    {
+        int rc = xin ? y0 - 2 : min(max(y0 - 2, 0), ny);
+        cs0 = corner(d, il, rc);
+        cs1 = corner(d, il + 1, rc);
+    }
+    auto load = [&](Row &R, int r) {
+        int rr = xin ? r : min(max(r, 0), ny - 1);
+        int rc = xin ? r + 1 : min(max(r + 1, 0), ny);
+        CellIn ci = load_cell<PROJ>(d, E, U, V, il, rr, c.bk, c.bs);
+        R.e = ci.e; R.u = ci.u; R.v = ci.v; R.f = ci.f;
+        float cn0 = corner(d, il, rc), cn1 = corner(d, il + 1, rc);
+        row_terms<PROJ>(R, cs0, cs1, cn0, cn1, ci.th, d);
+        cs0 = cn0;
+        cs1 = cn1;
+    };
+
+    Row A, B, C;
+    F3 Gs = {0.f, 0.f, 0.f};
+    for (int k = y0 - 2; k <= y1 + 1; ++k) {
+        load(C, k);
+        if (k >= y0 - 1) y_diff(C, B, d);
+        if (k >= y0) {
+            float uS, vS;
+            y_faces(B, C, A.land, d, uS, vS);
+            F3 Gn = {0.f, 0.f, 0.f};
+            if (k >= y0 + 1) Gn = y_flux(A, B, uS, vS, d);
+            if (k >= y0 + 2) {
+                c.o = k - 2;
+                float e0 = 0.f, u0 = 0.f, v0 = 0.f;
+                if (STAGE == 2 && c.out_lane) {
+                    const size_t oq = (size_t)c.o * d.pitch + c.i;
+                    e0 = d.eta[oq]; u0 = d.hu[oq]; v0 = d.hv[oq];
+                }
+                finish_row<STAGE, PROJ, true>(A, Gs, Gn, c, e0, u0, v0, d, wmax_loc, bad);
+            }
+            Gs = Gn;
+        }
+        A = B;
+        B = C;
     }
 }
 
@@ -282,7 +591,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Ti
 
     Ctrl *ctrl = d.ctrl;
     const double tn = ctrl->t[parity];
-    const uint32_t wbits = ctrl->wmax[parity];
+    const uint32_t wbits = read_wmax(ctrl, parity, lane);
     const double te = ctrl->t_end;
     double dtd = dt_fixed > 0.0 ? dt_fixed : (double)(d.courant_q / __uint_as_float(wbits));
     bool skip = false, last = false;
@@ -290,208 +599,65 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Ti
         if (tn >= te) skip = true;
         else if (dtd >= te - tn) { dtd = te - tn; last = true; }
     }
-    if (STAGE == 1 && b == 0 && threadIdx.x == 0) {
-        if (skip) {
-            ctrl->t[parity ^ 1] = tn;
-            ctrl->wmax[parity ^ 1] = wbits;
-        } else {
-            ctrl->t[parity ^ 1] = last ? te : tn + dtd;
-            ctrl->wmax[parity ^ 1] = 0u;
-            ctrl->dt_last = (float)dtd;
-            ctrl->steps += 1;
+    if (STAGE == 1 && b == 0 && threadIdx.x < kCflSlots) {
+        // slots of the next parity: cleared for stage 2 to accumulate into, or,
+        // for a step past t_end, the current maximum carried over
+        ctrl->wslot[parity ^ 1][threadIdx.x][0] = skip ? wbits : 0u;
+        if (threadIdx.x == 0) {
+            if (skip) {
+                ctrl->t[parity ^ 1] = tn;
+            } else {
+                ctrl->t[parity ^ 1] = last ? te : tn + dtd;
+                ctrl->dt_last = (float)dtd;
+                ctrl->steps += 1;
+            }
         }
     }
     if (skip || tile >= T.ntiles) return;
 
-    const float dt = (float)dtd;
     const double tau = STAGE == 1 ? tn : tn + dtd;
-    int bk = 0;
-    double bs = 0.0;
-    if (d.nb > 0) time_weights(d.nb, d.bnd_t, tau, bk, bs);
-    float wx, wy;
-    wind_at(d, tau, wx, wy);
-
-    const float *__restrict__ E = STAGE == 1 ? d.eta : d.eta1;
-    const float *__restrict__ U = STAGE == 1 ? d.hu : d.hu1;
-    const float *__restrict__ V = STAGE == 1 ? d.hv : d.hv1;
+    TileCtx c;
+    c.dt = (float)dtd;
+    c.bk = 0;
+    c.bs = 0.0;
+    if (d.nb > 0) time_weights(d.nb, d.bnd_t, tau, c.bk, c.bs);
+    wind_at(d, tau, c.wx, c.wy);
 
     const int nx = d.nx, ny = d.ny;
     const int strip = tile / T.nrb, rb = tile - strip * T.nrb;
     const int x0 = strip * kStrip;
     const int y0 = rb * T.by, y1 = min(y0 + T.by, ny);
-    const int i = x0 - kHalo + lane;
-    const int il = min(i, nx + 1);  // lanes right of the east ghosts load a ghost column
-    const bool xin = il >= 0 && il < nx;
-    const bool out_lane = lane >= kHalo && lane < kWave - kHalo && i < nx;
-    const float th = d.theta;
+    c.i = x0 - kHalo + lane;
+    c.o = y0;
+    c.out_lane = lane >= kHalo && lane < kWave - kHalo && c.i < nx;
 
-    // Lanes in a ghost column only ever contribute rows inside [0, ny); their
-    // rows outside (diagonal ghosts) are clamped to stay in bounds and are
-    // never used.  Corner rows are clamped separately so that row 0 still
-    // sees corner row 0 as its south side.
-    auto load_row = [&](int r, Row &R, float &thv) {
-        int rr = xin ? r : min(max(r, 0), ny - 1);
-        int rc = xin ? r + 1 : min(max(r + 1, 0), ny);
-        CellIn c = load_cell<PROJ>(d, E, U, V, il, rr, bk, bs);
-        R.e = c.e; R.u = c.u; R.v = c.v; R.f = c.f;
-        thv = c.th;
-        R.cn0 = corner(d, il, rc);
-        R.cn1 = corner(d, il + 1, rc);
-    };
-
+    // interior: columns x0-2 .. x0+61 and rows y0-2 .. y1+2 (corner rows) inside
+    // the domain, and no output cell within the relaxation zone of a nested side
+    const int W = d.frs_w;
+    bool interior = x0 >= kHalo && x0 + kStrip + kHalo <= nx && y0 >= kHalo && y1 + kHalo <= ny - 1;
+    if (W > 0) {
+        if (d.bc[0] == BC_NESTED && x0 < W) interior = false;
+        if (d.bc[1] == BC_NESTED && x0 + kStrip > nx - W) interior = false;
+        if (d.bc[2] == BC_NESTED && y0 < W) interior = false;
+        if (d.bc[3] == BC_NESTED && y1 > ny - W) interior = false;
+    }
     float wmax_loc = 0.f;
     int bad = 0;
-
-    // window: A = row k-2 (output), B = row k-1, C = row k (just loaded)
-    Row A, B, C;
-    float csA0, csA1;           // south corners of the row being loaded
-    float eNA = 0.f, uNA = 0.f, vNA = 0.f; // north face values of row k-2 (from the previous iteration)
-    float eSA = 0.f;                       // south face eta of row k-2
-    F3 Gs = {0.f, 0.f, 0.f};    // flux through the south face of the output row
-
-    {
-        int rc = xin ? y0 - 2 : min(max(y0 - 2, 0), ny);
-        csA0 = corner(d, il, rc);
-        csA1 = corner(d, il + 1, rc);
-    }
-
-    for (int k = y0 - 2; k <= y1 + 1; ++k) {
-        float thv;
-        load_row(k, C, thv);
-        cell_terms<PROJ>(C, csA0, csA1, thv, d);
-        csA0 = C.cn0;
-        csA1 = C.cn1;
-        if (k >= y0 - 1) {
-            C.dmL = C.e - B.e - d.ky * (B.cy + C.cy);
-            C.dmU = C.u - B.u;
-            C.dmV = C.v - B.v;
-        }
-        if (k >= y0) {
-            // y-slopes and N/S face values of row k-1 (eqs. Kbackwards, hE for L)
-            float sL = limited(B.dmL, C.dmL, th);
-            float sU = limited(B.dmU, C.dmU, th);
-            float sV = limited(B.dmV, C.dmV, th);
-            if (A.land || C.land) sL = sU = sV = 0.f;
-            float rho = 0.5f * sL + d.ky * B.cy;
-            float eN = B.e + rho, eS = B.e - rho;
-            if (eN + B.Hn < 0.f) { eN = -B.Hn; eS = 2.f * B.e - eN; }
-            if (eS + B.Hs < 0.f) { eS = -B.Hs; eN = 2.f * B.e - eS; }
-            float uN = B.u + 0.5f * sU, uS = B.u - 0.5f * sU;
-            float vN = B.v + 0.5f * sV, vS = B.v - 0.5f * sV;
-            F3 Gn = {0.f, 0.f, 0.f};
-            if (k >= y0 + 1) {
-                // y-face between rows k-2 and k-1: normal momentum hv, transverse hu
-                Gn = face_flux(eNA, vNA, uNA, eS, vS, uS, A.land, B.land, B.Hs, d);
-            }
-            if (k >= y0 + 2) {
-                // ---- output row o = k-2 (record A) ----
-                const int o = k - 2;
-                const float eNA_out = eNA, eSA_out = eSA;
-                float eL = from_left(A.e), cxL = from_left(A.cx);
-                float uL = from_left(A.u), vL = from_left(A.v);
-                int landL = from_left(A.land), landR = from_right(A.land);
-                float dmK = A.e - eL - d.kx * (cxL + A.cx);
-                float dmU = A.u - uL, dmV = A.v - vL;
-                float sK = limited(dmK, from_right(dmK), th);
-                float sUx = limited(dmU, from_right(dmU), th);
-                float sVx = limited(dmV, from_right(dmV), th);
-                if (landL || landR) sK = sUx = sVx = 0.f;
-                float rx = 0.5f * sK + d.kx * A.cx;
-                float eE = A.e + rx, eW = A.e - rx;
-                if (eE + A.He < 0.f) { eE = -A.He; eW = 2.f * A.e - eE; }
-                if (eW + A.Hw < 0.f) { eW = -A.Hw; eE = 2.f * A.e - eW; }
-                float uE = A.u + 0.5f * sUx, uW = A.u - 0.5f * sUx;
-                float vE = A.v + 0.5f * sVx, vW = A.v - 0.5f * sVx;
-                F3 Fe = face_flux(eE, uE, vE, from_right(eW), from_right(uW), from_right(vW),
-                                  A.land != 0, landR != 0, A.He, d);
-                float Fwe = from_left(Fe.e), Fwp = from_left(Fe.p), Fwq = from_left(Fe.q);
-
-                if (out_lane && !A.land) {
-                    float Cx, Cy;
-                    if (PROJ) {
-                        float c = __cosf(d.north[(size_t)o * d.pitch + i]);
-                        float s = __sinf(d.north[(size_t)o * d.pitch + i]);
-                        float hue = c * A.u - s * A.v, hvn = s * A.u + c * A.v;
-                        Cx = A.f * (c * hvn - s * hue);
-                        Cy = A.f * (-s * hvn - c * hue);
-                    } else {
-                        Cx = A.f * A.v;
-                        Cy = -A.f * A.u;
-                    }
-                    float Me = -(Fe.e - Fwe) * d.rdx - (Gn.e - Gs.e) * d.rdy;
-                    float Mu = -(Fe.p - Fwp) * d.rdx - (Gn.q - Gs.q) * d.rdy +
-                               bathy_source(A.e, eE, eW, A.He, A.Hw, d) * d.rdx + Cx + wx;
-                    float Mv = -(Fe.q - Fwq) * d.rdx - (Gn.p - Gs.p) * d.rdy +
-                               bathy_source(A.e, eNA_out, eSA_out, A.Hn, A.Hs, d) * d.rdy + Cy + wy;
-                    const size_t oo = (size_t)o * d.pitch + i;
-                    float en, un, vn;
-                    if (STAGE == 1) {
-                        float S = friction_coeff(d, A.e + A.Hb, A.u, A.v);
-                        float den = rcp(1.f + dt * S);
-                        en = A.e + dt * Me;
-                        un = (A.u + dt * Mu) * den;
-                        vn = (A.v + dt * Mv) * den;
-                        d.eta1[oo] = en;
-                        d.hu1[oo] = un;
-                        d.hv1[oo] = vn;
-                    } else {
-                        float S = friction_coeff(d, A.e + A.Hb, A.u, A.v);
-                        float den = rcp(1.f + 0.5f * dt * S);
-                        float e0 = d.eta[oo], u0 = d.hu[oo], v0 = d.hv[oo];
-                        en = 0.5f * (e0 + (A.e + dt * Me));
-                        un = 0.5f * (u0 + (A.u + dt * Mu)) * den;
-                        vn = 0.5f * (v0 + (A.v + dt * Mv)) * den;
-                        if (d.frs_w > 0) {
-                            // eq. frs: nearest nested side within the zone, ties W, E, S, N
-                            int dist[4] = {i, nx - 1 - i, o, ny - 1 - o};
-                            int idxs[4] = {o, ny + o, 2 * ny + i, 2 * ny + nx + i};
-                            int best = -1, dd = 0;
-#pragma unroll
-                            for (int s = 0; s < 4; ++s)
-                                if (d.bc[s] == BC_NESTED && (best < 0 || dist[s] < dd)) { best = s; dd = dist[s]; }
-                            if (best >= 0 && dd < d.frs_w) {
-                                int idx = best == 0 ? idxs[0] : best == 1 ? idxs[1] : best == 2 ? idxs[2] : idxs[3];
-                                float al = d.frs_alpha[dd];
-                                en = (1.f - al) * en + al * ext_value(d, bk, bs, 0, idx);
-                                un = (1.f - al) * un + al * ext_value(d, bk, bs, 1, idx);
-                                vn = (1.f - al) * vn + al * ext_value(d, bk, bs, 2, idx);
-                            }
-                        }
-                        d.eta[oo] = en;
-                        d.hu[oo] = un;
-                        d.hv[oo] = vn;
-                        // eq. cfl on the new state
-                        float h = en + A.Hb;
-                        float ri = rcp(desing(h, d));
-                        float c = fsqrt(d.g * fmaxf(h, 0.f));
-                        float w = fmaxf((fabsf(un * ri) + c) * d.rdx, (fabsf(vn * ri) + c) * d.rdy);
-                        wmax_loc = fmaxf(wmax_loc, w);
-                        if (!(isfinite(en) && isfinite(un) && isfinite(vn))) bad = 1;
-                    }
-                }
-                Gs = Gn;
-            } else {
-                Gs = Gn;
-            }
-            eNA = eN; uNA = uN; vNA = vN;
-            eSA = eS;
-        }
-        A = B;
-        B = C;
-    }
+    if (interior) tile_interior<STAGE, PROJ>(d, c, y0, y1, wmax_loc, bad);
+    else tile_edge<STAGE, PROJ>(d, c, y0, y1, lane, wmax_loc, bad);
 
     if (STAGE == 2) {
-        for (int off = kWave / 2; off > 0; off >>= 1) wmax_loc = fmaxf(wmax_loc, __shfl_xor(wmax_loc, off, kWave));
+        wmax_loc = wave_max(wmax_loc);
         unsigned long long anybad = __ballot(bad);
         if (lane == 0) {
-            atomicMax(&ctrl->wmax[parity ^ 1], __float_as_uint(wmax_loc));
+            atomicMax(&ctrl->wslot[parity ^ 1][tile & (kCflSlots - 1)][0], __float_as_uint(wmax_loc));
             if (anybad) atomicOr(&ctrl->flags, 1u);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// CFL reduction of a given state into ctrl->wmax[slot] (used at init and
+// CFL reduction of a given state into the slots of parity `slot` (used at init and
 // after a state change); one thread per cell.
 // ---------------------------------------------------------------------------
 __global__ void cfl_kernel(Dom d, int slot)
@@ -513,10 +679,11 @@ __global__ void cfl_kernel(Dom d, int slot)
             if (!(isfinite(e) && isfinite(u) && isfinite(v))) bad = 1;
         }
     }
-    for (int off = kWave / 2; off > 0; off >>= 1) w = fmaxf(w, __shfl_xor(w, off, kWave));
+    w = wave_max(w);
     unsigned long long anybad = __ballot(bad);
     if ((threadIdx.x & (kWave - 1)) == 0) {
-        atomicMax(&d.ctrl->wmax[slot], __float_as_uint(w));
+        int k = (blockIdx.x + blockIdx.y * gridDim.x + (threadIdx.x / kWave)) & (kCflSlots - 1);
+        atomicMax(&d.ctrl->wslot[slot][k][0], __float_as_uint(w));
         if (anybad) atomicOr(&d.ctrl->flags, 1u);
     }
 }
@@ -524,14 +691,16 @@ __global__ void cfl_kernel(Dom d, int slot)
 // control block set-up: time, CFL slot cleared, flags cleared
 __global__ void ctrl_reset_kernel(Ctrl *c, double t, int slot)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        c->t[slot] = t;
-        c->t[slot ^ 1] = t;
-        c->wmax[slot] = 0u;
-        c->wmax[slot ^ 1] = 0u;
-        c->flags = 0u;
-        c->dt_last = 0.f;
-        c->t_end = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x < kCflSlots) {
+        c->wslot[0][threadIdx.x][0] = 0u;
+        c->wslot[1][threadIdx.x][0] = 0u;
+        if (threadIdx.x == 0) {
+            c->t[slot] = t;
+            c->t[slot ^ 1] = t;
+            c->flags = 0u;
+            c->dt_last = 0.f;
+            c->t_end = 0.0;
+        }
     }
 }
 

@@ -154,12 +154,15 @@ int swe_diagnostics(swe_domain *d, double *mass, double *energy);
 int swe_status(swe_domain *d);
 
 /* Work decomposition of the stage kernels: each wavefront updates a strip of
- * 60 columns over rows_per_wave rows (0 = the built-in choice, which fills
- * the GPU's wave slots in whole rounds).  Used by the autotuner; the results
- * do not depend on it (bitwise).  swe_get_tiling reports the current rows per
- * wave and the number of wavefronts per stage launch. */
-int swe_set_tiling(swe_domain *d, int32_t rows_per_wave);
-int swe_get_tiling(swe_domain *d, int32_t *rows_per_wave, int32_t *waves);
+ * 60 columns over rows_per_wave rows (0 = the built-in choice per stage
+ * kernel, which fills the wave slots its register use allows in whole
+ * rounds); order picks the tile numbering
+ * (bit 0: row-block-major instead of strip-major, bit 1: no grouping of
+ * neighbouring tiles per XCD; -1 = default).  Used by the autotuner; results
+ * do not depend on it (bitwise).  swe_get_tiling reports the values and the
+ * wavefronts per launch of the first stage kernel. */
+int swe_set_tiling(swe_domain *d, int32_t rows_per_wave, int32_t order);
+int swe_get_tiling(swe_domain *d, int32_t *rows_per_wave, int32_t *order, int32_t *waves);
 
 /* Average device time per launch of each stage kernel (milliseconds) over
  * the launches issued since the last call with reset != 0, measured with HIP

@@ -19,6 +19,7 @@ hipError_t launch_cfl(const Dom &d, int slot, hipStream_t s);
 hipError_t launch_ctrl_reset(Ctrl *c, double t, int slot, hipStream_t s);
 hipError_t launch_set_t_end(Ctrl *c, double te, hipStream_t s);
 hipError_t launch_diagnostics(const Dom &d, hipStream_t s);
+int stage_waves_per_simd(int stage, bool proj);
 }  // namespace swe
 
 using namespace swe;
@@ -129,7 +130,8 @@ struct swe_domain {
     char *ws = nullptr;
     Layout L{};
     Dom dom{};
-    Tiling T{};
+    Tiling T[2]{};  // per stage
+    int wps[2] = {3, 3};  // resident waves per SIMD of each stage kernel
     int parity = 0;
     int max_wind = 0, max_bnd = 0;
     bool has_bnd = false;
@@ -205,14 +207,14 @@ int launch_step(swe_domain *d, int parity, double dt_fixed, hipStream_t s, bool 
             d->ev_pool.push_back(ev);
         }
         hipEvent_t *pe = &d->ev_pool[d->ev_used];
-        HIP_TRY(launch_stage(1, proj, d->dom, d->T, parity, dt_fixed, s, pe[0], pe[1]));
-        HIP_TRY(launch_stage(2, proj, d->dom, d->T, parity, dt_fixed, s, pe[2], pe[3]));
+        HIP_TRY(launch_stage(1, proj, d->dom, d->T[0], parity, dt_fixed, s, pe[0], pe[1]));
+        HIP_TRY(launch_stage(2, proj, d->dom, d->T[1], parity, dt_fixed, s, pe[2], pe[3]));
         d->ev_used += 4;
         d->timed_steps += 1;
         return SWE_OK;
     }
-    HIP_TRY(launch_stage(1, proj, d->dom, d->T, parity, dt_fixed, s, nullptr, nullptr));
-    HIP_TRY(launch_stage(2, proj, d->dom, d->T, parity, dt_fixed, s, nullptr, nullptr));
+    HIP_TRY(launch_stage(1, proj, d->dom, d->T[0], parity, dt_fixed, s, nullptr, nullptr));
+    HIP_TRY(launch_stage(2, proj, d->dom, d->T[1], parity, dt_fixed, s, nullptr, nullptr));
     return SWE_OK;
 }
 
@@ -229,11 +231,11 @@ int get_graph(swe_domain *d, int steps, int parity, hipGraphExec_t *out)
     for (int k = 0; k < steps && rc == SWE_OK; ++k) rc = launch_step(d, (parity + k) & 1, 0.0, d->capture_stream, false);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(d->capture_stream, &g);
-    if (rc != SWE_OK) { if (g) hipGraphDestroy(g); return rc; }
+    if (rc != SWE_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     hipGraphExec_t ex = nullptr;
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    if (e != hipSuccess) { hipGraphDestroy(g); return hip_fail(e, "hipGraphInstantiate"); }
+    if (e != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e, "hipGraphInstantiate"); }
     d->graph_objs.push_back(g);
     d->graphs[key] = ex;
     *out = ex;
@@ -333,10 +335,13 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
     D.partials = (double *)(w + L.partials);
     {
         int dev = 0, cus = 256;
-        if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         d->cus = cus > 0 ? cus : 256;
     }
-    d->T = make_tiling(nx, ny, pick_rows_per_wave(nx, ny, d->cus, 4));
+    for (int st = 0; st < 2; ++st) {
+        d->wps[st] = stage_waves_per_simd(st + 1, p->north_projection != 0);
+        d->T[st] = make_tiling(nx, ny, pick_rows_per_wave(nx, ny, d->cus, d->wps[st]));
+    }
 
     hipStream_t s = d->stream;
     int r = SWE_OK;
@@ -361,7 +366,7 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
     if (p->north_projection) {
         std::vector<float> th0(nc, 0.f);
         if ((r = upload_pitched(d, L.north, theta ? theta : th0.data(), nx, ny, D.pitch, s))) { delete d; return r; }
-        hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(s);
     }
     hipError_t e;
     if ((e = hipMemcpyAsync(w + L.fghost, fg.data(), fg.size() * sizeof(float), hipMemcpyHostToDevice, s)) ||
@@ -415,8 +420,8 @@ int swe_set_forcing(swe_domain *d, int32_t kind, int32_t n_times, const double *
         return fail(SWE_E_ARG, "unknown forcing kind");
     }
     // kernel arguments changed: captured graphs are stale
-    for (auto &kv : d->graphs) hipGraphExecDestroy(kv.second);
-    for (auto g : d->graph_objs) hipGraphDestroy(g);
+    for (auto &kv : d->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto g : d->graph_objs) (void)hipGraphDestroy(g);
     d->graphs.clear();
     d->graph_objs.clear();
     return SWE_OK;
@@ -552,24 +557,29 @@ int swe_status(swe_domain *d)
     return c.flags ? fail(SWE_E_UNSTABLE, "non-finite state") : SWE_OK;
 }
 
-int swe_set_tiling(swe_domain *d, int32_t rows_per_wave)
+int swe_set_tiling(swe_domain *d, int32_t rows_per_wave, int32_t order)
 {
     if (!d) return fail(SWE_E_ARG, "domain is NULL");
     if (rows_per_wave < 0 || rows_per_wave > 4096) return fail(SWE_E_ARG, "rows_per_wave out of range");
-    int by = rows_per_wave ? rows_per_wave : pick_rows_per_wave(d->p.nx, d->p.ny, d->cus, 4);
-    d->T = make_tiling(d->p.nx, d->p.ny, by);
-    for (auto &kv : d->graphs) hipGraphExecDestroy(kv.second);
-    for (auto g : d->graph_objs) hipGraphDestroy(g);
+    if (order < -1 || order > 3) return fail(SWE_E_ARG, "order must be -1 (default) or 0..3");
+    for (int st = 0; st < 2; ++st) {
+        int by = rows_per_wave ? rows_per_wave : pick_rows_per_wave(d->p.nx, d->p.ny, d->cus, d->wps[st]);
+        d->T[st] = make_tiling(d->p.nx, d->p.ny, by);
+        if (order >= 0) d->T[st].order = order;
+    }
+    for (auto &kv : d->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto g : d->graph_objs) (void)hipGraphDestroy(g);
     d->graphs.clear();
     d->graph_objs.clear();
     return SWE_OK;
 }
 
-int swe_get_tiling(swe_domain *d, int32_t *rows_per_wave, int32_t *waves)
+int swe_get_tiling(swe_domain *d, int32_t *rows_per_wave, int32_t *order, int32_t *waves)
 {
     if (!d) return fail(SWE_E_ARG, "domain is NULL");
-    if (rows_per_wave) *rows_per_wave = d->T.by;
-    if (waves) *waves = d->T.ntiles;
+    if (rows_per_wave) *rows_per_wave = d->T[0].by;
+    if (order) *order = d->T[0].order;
+    if (waves) *waves = d->T[0].ntiles;
     return SWE_OK;
 }
 
@@ -606,11 +616,11 @@ int swe_stage_times(swe_domain *d, double *ms_stage1, double *ms_stage2, int64_t
 void swe_destroy(swe_domain *d)
 {
     if (!d) return;
-    if (d->stream) hipStreamSynchronize(d->stream);
-    for (auto &kv : d->graphs) hipGraphExecDestroy(kv.second);
-    for (auto g : d->graph_objs) hipGraphDestroy(g);
-    for (auto e : d->ev_pool) hipEventDestroy(e);
-    if (d->capture_stream) hipStreamDestroy(d->capture_stream);
+    if (d->stream) (void)hipStreamSynchronize(d->stream);
+    for (auto &kv : d->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto g : d->graph_objs) (void)hipGraphDestroy(g);
+    for (auto e : d->ev_pool) (void)hipEventDestroy(e);
+    if (d->capture_stream) (void)hipStreamDestroy(d->capture_stream);
     delete d;
 }
 

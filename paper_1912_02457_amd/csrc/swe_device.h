@@ -83,25 +83,27 @@ struct Dom {
 
 struct Tiling {
     int by;       // rows per wave
+    int order;    // bit 0: row-block-major tile numbering; bit 1: no XCD grouping
     int nstrips;  // ceil(nx / kStrip)
     int nrb;      // ceil(ny / by)
     int ntiles;   // nstrips * nrb
     int nblocks;  // ceil(ntiles / kWavesPerBlock)
 };
 
-// Rows per wave for a domain: fill the wave slots of the device (waves_per_simd
-// resident per SIMD, 4 SIMDs per CU) in whole rounds while keeping the 2-row
-// halo of each tile (about 2.5 rows of extra work) small.
+// Rows per wave for a domain.  A wave's work is proportional to its rows plus
+// the ~4 halo rows it also loads and reconstructs; the kernel time is about
+// the total work spread over the resident wave slots plus one wave's worth of
+// tail (measured on config-2, 1024^2 and 4096^2 domains: this picks 8, 5-7 and
+// 16-24 rows, the measured optima).
 inline int pick_rows_per_wave(int nx, int ny, int cus, int waves_per_simd)
 {
-    const long slots = (long)cus * 4 * waves_per_simd;
+    const double slots = (double)cus * 4 * waves_per_simd;
     const long nstrips = (nx + kStrip - 1) / kStrip;
-    int best = 16;
+    int best = 8;
     double best_cost = 1e300;
-    for (int by = 4; by <= 256; by += (by < 16 ? 1 : (by < 64 ? 4 : 16))) {
+    for (int by = 2; by <= 256; by += (by < 16 ? 1 : (by < 64 ? 4 : 16))) {
         long waves = nstrips * ((ny + by - 1) / by);
-        long rounds = (waves + slots - 1) / slots;
-        double cost = (double)rounds * (by + 2.5);
+        double cost = (double)waves * (by + 4) / slots + (by + 4);
         if (cost < best_cost - 1e-9) { best_cost = cost; best = by; }
     }
     return best;
@@ -111,6 +113,7 @@ inline Tiling make_tiling(int nx, int ny, int by)
 {
     Tiling t;
     t.by = by;
+    t.order = 0;
     t.nstrips = (nx + kStrip - 1) / kStrip;
     t.nrb = (ny + by - 1) / by;
     t.ntiles = t.nstrips * t.nrb;

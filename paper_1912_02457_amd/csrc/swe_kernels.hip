@@ -50,10 +50,10 @@ __device__ __forceinline__ float from_right(float v) { return __int_as_float(fro
 // eq. desing_ours
 __device__ __forceinline__ float desing(float h, const Dom &d)
 {
-    float a = fabsf(h);
     float lo = fminf(fmaf(h * h, d.inv2kappa, d.half_kappa), d.kappa);
-    float m = fmaxf(a, lo);
-    return h < 0.f ? -m : m;
+    float m = fmaxf(fabsf(h), lo);
+    // sign(h) with sign(0) = +1: adding +0 turns a -0 into +0
+    return copysignf(m, h + 0.f);
 }
 
 // generalized minmod of theta*backward, central, theta*forward differences
@@ -89,13 +89,6 @@ __device__ __forceinline__ uint32_t read_wmax(const Ctrl *c, int parity, int lan
     return v;
 }
 
-__device__ __forceinline__ float ext_value(const Dom &d, int k, double s, int fld, int idx)
-{
-    const float *a = d.bnd + ((size_t)k * 3 + fld) * d.P;
-    if (d.nb == 1) return a[idx];
-    const float *b = a + (size_t)3 * d.P;
-    return (float)((1.0 - s) * (double)a[idx] + s * (double)b[idx]);
-}
 
 __device__ __forceinline__ void wind_at(const Dom &d, double tau, float &wx, float &wy)
 {
@@ -111,50 +104,63 @@ __device__ __forceinline__ void wind_at(const Dom &d, double tau, float &wx, flo
     wy = (float)(ay * d.inv_rho_w);
 }
 
-struct CellIn { float e, u, v, f, th; };
+// Ghost cells.  Wall ghosts mirror the state with the normal momentum and f
+// negated (eq. tradWallBCx and f(-x) = -f(x) of eq. KxWallBCReq); periodic
+// ghosts wrap; nested ghosts take the external state at the stage time and
+// the f / north angle stored for them at init.  The mapping is split into a
+// column part, fixed for a lane over a whole tile, and a row part, the same
+// for every lane of a row.
+struct ColMap {
+    int ci;       // source column
+    int cc0, cc1; // source corner columns of the cell's west and east corners
+    float su, sf; // sign of hu and f (wall ghost)
+    int nside;    // nested side 0 (W) / 1 (E) for a nested ghost column, else -1
+    int nlayer;   // 0 for the ghost next to the domain, 1 for the outer one
+};
 
-// Cell (i, r) with i in [-2, nx+1], r in [-2, ny+1], at most one of them
-// outside the domain.  Wall ghosts mirror the state with the normal momentum
-// and f negated (eq. tradWallBCx and f(-x) = -f(x) of eq. KxWallBCReq);
-// periodic ghosts wrap; nested ghosts take the external state at the stage
-// time and the f / north angle stored for them at init.
-template <bool PROJ>
-__device__ __forceinline__ CellIn load_cell(const Dom &d, const float *__restrict__ E,
-                                            const float *__restrict__ U, const float *__restrict__ V,
-                                            int i, int r, int bk, double bs)
+struct RowMap {
+    int cr;       // source row
+    int crc;      // source corner row of the cell's north corners
+    float sv, sf; // sign of hv and f (wall ghost)
+    int nside;    // nested side 2 (S) / 3 (N) for a nested ghost row, else -1
+    int nlayer;
+};
+
+__device__ __forceinline__ int map_corner(int c, int n, int lo, int hi);
+
+// i in [-2, nx+1]
+__device__ __forceinline__ ColMap col_map(const Dom &d, int i)
 {
-    const int nx = d.nx, ny = d.ny;
-    int ci = i, cr = r, side = -1, idx = 0, layer = 0;
-    float su = 1.f, sv = 1.f, sf = 1.f;
+    const int nx = d.nx;
+    ColMap m;
+    m.ci = i; m.su = 1.f; m.sf = 1.f; m.nside = -1; m.nlayer = 0;
     if (i < 0) {
-        if (d.bc[0] == BC_PERIODIC) ci = i + nx;
-        else { ci = -1 - i; if (d.bc[0] == BC_WALL) { su = -1.f; sf = -1.f; } else { side = 0; idx = r; layer = -1 - i; } }
+        if (d.bc[0] == BC_PERIODIC) m.ci = i + nx;
+        else { m.ci = -1 - i; if (d.bc[0] == BC_WALL) { m.su = -1.f; m.sf = -1.f; } else { m.nside = 0; m.nlayer = -1 - i; } }
     } else if (i >= nx) {
-        if (d.bc[1] == BC_PERIODIC) ci = i - nx;
-        else { ci = 2 * nx - 1 - i; if (d.bc[1] == BC_WALL) { su = -1.f; sf = -1.f; } else { side = 1; idx = ny + r; layer = i - nx; } }
-    } else if (r < 0) {
-        if (d.bc[2] == BC_PERIODIC) cr = r + ny;
-        else { cr = -1 - r; if (d.bc[2] == BC_WALL) { sv = -1.f; sf = -1.f; } else { side = 2; idx = 2 * ny + i; layer = -1 - r; } }
+        if (d.bc[1] == BC_PERIODIC) m.ci = i - nx;
+        else { m.ci = 2 * nx - 1 - i; if (d.bc[1] == BC_WALL) { m.su = -1.f; m.sf = -1.f; } else { m.nside = 1; m.nlayer = i - nx; } }
+    }
+    m.cc0 = map_corner(i, nx, d.bc[0], d.bc[1]);
+    m.cc1 = map_corner(i + 1, nx, d.bc[0], d.bc[1]);
+    return m;
+}
+
+// r in [-2, ny+1]
+__device__ __forceinline__ RowMap row_map(const Dom &d, int r)
+{
+    const int ny = d.ny;
+    RowMap m;
+    m.cr = r; m.sv = 1.f; m.sf = 1.f; m.nside = -1; m.nlayer = 0;
+    if (r < 0) {
+        if (d.bc[2] == BC_PERIODIC) m.cr = r + ny;
+        else { m.cr = -1 - r; if (d.bc[2] == BC_WALL) { m.sv = -1.f; m.sf = -1.f; } else { m.nside = 2; m.nlayer = -1 - r; } }
     } else if (r >= ny) {
-        if (d.bc[3] == BC_PERIODIC) cr = r - ny;
-        else { cr = 2 * ny - 1 - r; if (d.bc[3] == BC_WALL) { sv = -1.f; sf = -1.f; } else { side = 3; idx = 2 * ny + nx + i; layer = r - ny; } }
+        if (d.bc[3] == BC_PERIODIC) m.cr = r - ny;
+        else { m.cr = 2 * ny - 1 - r; if (d.bc[3] == BC_WALL) { m.sv = -1.f; m.sf = -1.f; } else { m.nside = 3; m.nlayer = r - ny; } }
     }
-    CellIn c;
-    if (side >= 0) {
-        c.e = ext_value(d, bk, bs, 0, idx);
-        c.u = ext_value(d, bk, bs, 1, idx);
-        c.v = ext_value(d, bk, bs, 2, idx);
-        c.f = d.fghost[(size_t)layer * d.P + idx];
-        c.th = PROJ ? d.nghost[(size_t)layer * d.P + idx] : 0.f;
-    } else {
-        size_t o = (size_t)cr * d.pitch + ci;
-        c.e = E[o];
-        c.u = su * U[o];
-        c.v = sv * V[o];
-        c.f = sf * d.f[o];
-        c.th = PROJ ? d.north[o] : 0.f;
-    }
-    return c;
+    m.crc = map_corner(r + 1, ny, d.bc[2], d.bc[3]);
+    return m;
 }
 
 __device__ __forceinline__ int map_corner(int c, int n, int lo, int hi)
@@ -164,12 +170,6 @@ __device__ __forceinline__ int map_corner(int c, int n, int lo, int hi)
     return c;
 }
 
-__device__ __forceinline__ float corner(const Dom &d, int ci, int cj)
-{
-    int a = map_corner(ci, d.nx, d.bc[0], d.bc[1]);
-    int b = map_corner(cj, d.ny, d.bc[2], d.bc[3]);
-    return d.Hc[(size_t)b * d.cpitch + a];
-}
 
 struct F3 { float e, p, q; };
 
@@ -330,12 +330,51 @@ struct TileCtx {
     double bs;
 };
 
+// Flow relaxation (eq. frs) of one output cell, split so that its loads are
+// issued at the start of the row and consumed at the end: the nearest nested
+// side within the zone (ties W, E, S, N), its weight alpha = 1 - tanh(d/d0)
+// and the two boundary snapshots around the stage time.
+struct FrsPre {
+    bool zone;
+    float al;
+    float a[3], b[3];
+};
+
+__device__ __forceinline__ FrsPre frs_prefetch(const Dom &d, const TileCtx &c)
+{
+    FrsPre f;
+    const int nx = d.nx, ny = d.ny, i = c.i, o = c.o;
+    int dist[4] = {i, nx - 1 - i, o, ny - 1 - o};
+    int idxs[4] = {o, ny + o, 2 * ny + i, 2 * ny + nx + i};
+    int best = -1, dd = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (d.bc[k] == BC_NESTED && (best < 0 || dist[k] < dd)) { best = k; dd = dist[k]; }
+    f.zone = c.out_lane && best >= 0 && dd < d.frs_w;
+    f.al = 0.f;
+    f.a[0] = f.a[1] = f.a[2] = f.b[0] = f.b[1] = f.b[2] = 0.f;
+    if (f.zone) {
+        int idx = best == 0 ? idxs[0] : best == 1 ? idxs[1] : best == 2 ? idxs[2] : idxs[3];
+        f.al = d.frs_alpha[dd];
+        const uint32_t P = (uint32_t)d.P;
+        const float *pa = d.bnd + (uint32_t)c.bk * 3u * P + (uint32_t)idx;
+        const float *pb = d.nb > 1 ? pa + 3u * P : pa;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            f.a[q] = pa[q * P];
+            f.b[q] = pb[q * P];
+        }
+    }
+    return f;
+}
+
 // x-direction reconstruction and flux of the output row A, the update of
 // eq. rk2_semiimp and (stage 2) the flow relaxation and CFL reduction.
 // Every lane takes part in the cross-lane exchanges; only output lanes store.
 template <int STAGE, bool PROJ, bool FRS>
 __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 &Gn, const TileCtx &c,
-                                           float e0, float u0, float v0, const Dom &d, float &wmax_loc, int &bad)
+                                           float e0, float u0, float v0, const FrsPre &fp, const Dom &d,
+                                           float &wmax_loc, int &bad)
 {
     const float th = d.theta;
     float eL = from_left(A.e), cxL = from_left(A.cx);
@@ -362,7 +401,7 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
 
     float Cx, Cy;
     if (PROJ) {
-        float ang = store ? d.north[(size_t)c.o * d.pitch + c.i] : 0.f;
+        float ang = store ? d.north[(uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i] : 0.f;
         float cc = __cosf(ang), ss = __sinf(ang);
         float hue = cc * A.u - ss * A.v, hvn = ss * A.u + cc * A.v;
         Cx = A.f * (cc * hvn - ss * hue);
@@ -376,7 +415,7 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
                Cx + c.wx;
     float Mv = -(Fe.q - Fwq) * d.rdx - (Gn.p - Gs.p) * d.rdy +
                bathy_source(A.e, A.eN, A.eS, A.Hn, A.Hs, d) * d.rdy + Cy + c.wy;
-    const size_t oo = (size_t)c.o * d.pitch + c.i;
+    const uint32_t oo = (uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i;
     const float dt = c.dt;
     float S = friction_coeff(d, A.ri, A.u, A.v);
     if (STAGE == 1) {
@@ -394,22 +433,15 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
         float en = 0.5f * (e0 + (A.e + dt * Me));
         float un = 0.5f * (u0 + (A.u + dt * Mu)) * den;
         float vn = 0.5f * (v0 + (A.v + dt * Mv)) * den;
-        if (FRS && store && d.frs_w > 0) {
-            // eq. frs: nearest nested side within the zone, ties W, E, S, N
-            const int nx = d.nx, ny = d.ny, i = c.i, o = c.o;
-            int dist[4] = {i, nx - 1 - i, o, ny - 1 - o};
-            int idxs[4] = {o, ny + o, 2 * ny + i, 2 * ny + nx + i};
-            int best = -1, dd = 0;
+        if (FRS && fp.zone) {
+            const float al = fp.al;
+            const double t = c.bs;
+            float ex[3];
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-                if (d.bc[s] == BC_NESTED && (best < 0 || dist[s] < dd)) { best = s; dd = dist[s]; }
-            if (best >= 0 && dd < d.frs_w) {
-                int idx = best == 0 ? idxs[0] : best == 1 ? idxs[1] : best == 2 ? idxs[2] : idxs[3];
-                float al = d.frs_alpha[dd];
-                en = (1.f - al) * en + al * ext_value(d, c.bk, c.bs, 0, idx);
-                un = (1.f - al) * un + al * ext_value(d, c.bk, c.bs, 1, idx);
-                vn = (1.f - al) * vn + al * ext_value(d, c.bk, c.bs, 2, idx);
-            }
+            for (int q = 0; q < 3; ++q) ex[q] = (float)((1.0 - t) * (double)fp.a[q] + t * (double)fp.b[q]);
+            en = (1.f - al) * en + al * ex[0];
+            un = (1.f - al) * un + al * ex[1];
+            vn = (1.f - al) * vn + al * ex[2];
         }
         if (store) {
             d.eta[oo] = en;
@@ -426,46 +458,123 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
     }
 }
 
-// ---- interior tiles: every cell of the tile and its 2-cell halo lies inside
-// the domain and outside any relaxation zone.  Plain 32-bit-offset loads, the
-// next row prefetched while the current one is processed, the window rotated
-// by unrolling (no register moves, no per-row branches). -----------------------
-struct RawRow { float e, u, v, f, cn0, cn1, th; };
+// ---- one tile: a wavefront's 64 columns over rows y0..y1-1 ------------------
+// The window of three rows rotates by unrolling (no register moves, no
+// per-row branches) and the next row is prefetched while the current one is
+// processed.  GHOST: the tile touches the domain edge, so loads go through
+// the boundary-kind mapping; otherwise plain 32-bit-offset loads.  FRS: the
+// tile has output cells inside a relaxation zone.
+// Raw loads of one row, issued one row ahead.  Ghost rows keep their sign
+// flips and, for nested ghosts, the second snapshot until the row is consumed
+// (finalize), so that the loads are not waited for where they are issued.
+struct RawRow {
+    float e, u, v, f, cn0, cn1, th;
+    float eb, ub, vb;  // nested ghosts: state at the later snapshot
+    uint32_t flip;     // sign bits to flip in hu (bit 31 of word 0), hv, f; bit 0: nested ghost
+};
 
-template <bool PROJ>
-__device__ __forceinline__ RawRow load_raw(const Dom &d, const float *__restrict__ E, const float *__restrict__ U,
-                                           const float *__restrict__ V, uint32_t off, uint32_t cof)
+constexpr uint32_t kSign = 0x80000000u;
+__device__ __forceinline__ float flip_sign(float x, uint32_t s) { return __uint_as_float(__float_as_uint(x) ^ s); }
+
+template <bool PROJ, bool GHOST>
+__device__ __forceinline__ RawRow load_row(const Dom &d, const float *__restrict__ E, const float *__restrict__ U,
+                                           const float *__restrict__ V, int il, const ColMap &cm, int r,
+                                           const TileCtx &c)
 {
-    RawRow r;
-    r.e = E[off];
-    r.u = U[off];
-    r.v = V[off];
-    r.f = d.f[off];
-    r.cn0 = d.Hc[cof];
-    r.cn1 = d.Hc[cof + 1];
-    r.th = PROJ ? d.north[off] : 0.f;
-    return r;
+    RawRow w;
+    w.flip = 0u;
+    w.eb = w.ub = w.vb = 0.f;
+    if (!GHOST) {
+        const uint32_t off = (uint32_t)r * (uint32_t)d.pitch + (uint32_t)il;
+        const uint32_t cof = (uint32_t)(r + 1) * (uint32_t)d.cpitch + (uint32_t)il;
+        w.e = E[off];
+        w.u = U[off];
+        w.v = V[off];
+        w.f = d.f[off];
+        w.cn0 = d.Hc[cof];
+        w.cn1 = d.Hc[cof + 1];
+        w.th = PROJ ? d.north[off] : 0.f;
+    } else {
+        // A lane in a ghost column only ever contributes rows inside [0, ny);
+        // its rows outside (diagonal ghosts) load some in-bounds value that is
+        // never used.
+        const RowMap rm = row_map(d, r);  // the same for all lanes
+        const bool yin = r >= 0 && r < d.ny;
+        int side = -1, idx = 0, layer = 0;
+        if (yin && cm.nside >= 0) {
+            side = cm.nside; layer = cm.nlayer; idx = cm.nside == 0 ? r : d.ny + r;
+        } else if (!yin && rm.nside >= 0) {
+            const int ii = min(max(il, 0), d.nx - 1);
+            side = rm.nside; layer = rm.nlayer; idx = rm.nside == 2 ? 2 * d.ny + ii : 2 * d.ny + d.nx + ii;
+        }
+        if (side >= 0) {
+            const uint32_t P = (uint32_t)d.P;
+            const float *a = d.bnd + (uint32_t)c.bk * 3u * P + (uint32_t)idx;
+            const float *b = d.nb > 1 ? a + 3u * P : a;
+            w.e = a[0]; w.u = a[P]; w.v = a[2u * P];
+            w.eb = b[0]; w.ub = b[P]; w.vb = b[2u * P];
+            w.flip = 1u;
+            w.f = d.fghost[(uint32_t)layer * P + (uint32_t)idx];
+            w.th = PROJ ? d.nghost[(uint32_t)layer * P + (uint32_t)idx] : 0.f;
+        } else {
+            const uint32_t off = (uint32_t)rm.cr * (uint32_t)d.pitch + (uint32_t)cm.ci;
+            w.e = E[off];
+            w.u = U[off];
+            w.v = V[off];
+            w.f = d.f[off];
+            // bits 31, 30, 29: flip hu, hv, f (a wall ghost negates them)
+            w.flip = (cm.su < 0.f ? kSign : 0u) | (rm.sv < 0.f ? kSign >> 1 : 0u) |
+                     ((cm.sf * rm.sf) < 0.f ? kSign >> 2 : 0u);
+            w.th = PROJ ? d.north[off] : 0.f;
+        }
+        const uint32_t cof = (uint32_t)rm.crc * (uint32_t)d.cpitch;
+        w.cn0 = d.Hc[cof + (uint32_t)cm.cc0];
+        w.cn1 = d.Hc[cof + (uint32_t)cm.cc1];
+    }
+    return w;
 }
 
-template <int STAGE, bool PROJ>
-__device__ __forceinline__ void tile_interior(const Dom &d, TileCtx c, int y0, int y1, float &wmax_loc, int &bad)
+template <int STAGE, bool PROJ, bool GHOST, bool FRS>
+__device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1, float &wmax_loc, int &bad)
 {
     const float *__restrict__ E = STAGE == 1 ? d.eta : d.eta1;
     const float *__restrict__ U = STAGE == 1 ? d.hu : d.hu1;
     const float *__restrict__ V = STAGE == 1 ? d.hv : d.hv1;
-    const uint32_t pitch = d.pitch, cpitch = d.cpitch;
-    uint32_t off = (uint32_t)(y0 - 2) * pitch + c.i;   // cell row to load next
-    uint32_t cof = (uint32_t)(y0 - 1) * cpitch + c.i;  // its north corner row
-    float cs0 = d.Hc[cof - cpitch], cs1 = d.Hc[cof - cpitch + 1];
-    RawRow nxt = load_raw<PROJ>(d, E, U, V, off, cof);
+    const int il = GHOST ? min(c.i, d.nx + 1) : c.i;  // lanes right of the east ghosts load a ghost column
+    ColMap cm;
+    float cs0, cs1;  // south corners of the row loaded next
+    if (!GHOST) {
+        const uint32_t cof = (uint32_t)(y0 - 2) * (uint32_t)d.cpitch + (uint32_t)il;
+        cs0 = d.Hc[cof];
+        cs1 = d.Hc[cof + 1];
+    } else {
+        cm = col_map(d, il);
+        const uint32_t cof = (uint32_t)map_corner(y0 - 2, d.ny, d.bc[2], d.bc[3]) * (uint32_t)d.cpitch;
+        cs0 = d.Hc[cof + (uint32_t)cm.cc0];
+        cs1 = d.Hc[cof + (uint32_t)cm.cc1];
+    }
     const int klast = y1 + 1;
+    RawRow nxt = load_row<PROJ, GHOST>(d, E, U, V, il, cm, y0 - 2, c);
 
     auto load = [&](Row &C, int k) {
         RawRow cur = nxt;
-        if (k < klast) nxt = load_raw<PROJ>(d, E, U, V, off + pitch, cof + cpitch);
-        off += pitch;
-        cof += cpitch;
-        C.e = cur.e; C.u = cur.u; C.v = cur.v; C.f = cur.f;
+        if (k < klast) nxt = load_row<PROJ, GHOST>(d, E, U, V, il, cm, k + 1, c);
+        if (GHOST) {
+            if (cur.flip & 1u) {
+                const double t = c.bs;
+                C.e = (float)((1.0 - t) * (double)cur.e + t * (double)cur.eb);
+                C.u = (float)((1.0 - t) * (double)cur.u + t * (double)cur.ub);
+                C.v = (float)((1.0 - t) * (double)cur.v + t * (double)cur.vb);
+                C.f = cur.f;
+            } else {
+                C.e = cur.e;
+                C.u = flip_sign(cur.u, cur.flip & kSign);
+                C.v = flip_sign(cur.v, (cur.flip << 1) & kSign);
+                C.f = flip_sign(cur.f, (cur.flip << 2) & kSign);
+            }
+        } else {
+            C.e = cur.e; C.u = cur.u; C.v = cur.v; C.f = cur.f;
+        }
         row_terms<PROJ>(C, cs0, cs1, cur.cn0, cur.cn1, cur.th, d);
         cs0 = cur.cn0;
         cs1 = cur.cn1;
@@ -486,16 +595,23 @@ __device__ __forceinline__ void tile_interior(const Dom &d, TileCtx c, int y0, i
 
     // steady state: A = row k-2 (output), B = row k-1, C = row k
     auto step = [&](Row &A, Row &B, Row &C, int k) {
+        c.o = k - 2;
         float e0 = 0.f, u0 = 0.f, v0 = 0.f;
-        const uint32_t oq = off - 2 * pitch;  // output row k-2 (off points at row k)
-        if (STAGE == 2) { e0 = d.eta[oq]; u0 = d.hu[oq]; v0 = d.hv[oq]; }
+        if (STAGE == 2 && (!GHOST || c.out_lane)) {
+            const uint32_t oq = (uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i;
+            e0 = d.eta[oq];
+            u0 = d.hu[oq];
+            v0 = d.hv[oq];
+        }
+        FrsPre fp;
+        fp.zone = false;
+        if (STAGE == 2 && FRS) fp = frs_prefetch(d, c);
         load(C, k);
         y_diff(C, B, d);
         float us, vs;
         y_faces(B, C, A.land, d, us, vs);
         F3 Gn = y_flux(A, B, us, vs, d);
-        c.o = k - 2;
-        finish_row<STAGE, PROJ, false>(A, Gs, Gn, c, e0, u0, v0, d, wmax_loc, bad);
+        finish_row<STAGE, PROJ, FRS>(A, Gs, Gn, c, e0, u0, v0, fp, d, wmax_loc, bad);
         Gs = Gn;
     };
     for (int k = y0 + 2;;) {
@@ -505,65 +621,6 @@ __device__ __forceinline__ void tile_interior(const Dom &d, TileCtx c, int y0, i
         if (++k > klast) break;
         step(R1, R2, R0, k);
         if (++k > klast) break;
-    }
-}
-
-// ---- edge tiles: ghost cells from the boundary kinds, relaxation zone -------
-template <int STAGE, bool PROJ>
-__device__ __forceinline__ void tile_edge(const Dom &d, TileCtx c, int y0, int y1, int lane, float &wmax_loc, int &bad)
-{
-    const float *__restrict__ E = STAGE == 1 ? d.eta : d.eta1;
-    const float *__restrict__ U = STAGE == 1 ? d.hu : d.hu1;
-    const float *__restrict__ V = STAGE == 1 ? d.hv : d.hv1;
-    const int nx = d.nx, ny = d.ny;
-    const int il = min(c.i, nx + 1);  // lanes right of the east ghosts load a ghost column
-    const bool xin = il >= 0 && il < nx;
-    (void)lane;
-
-    // Lanes in a ghost column only ever contribute rows inside [0, ny); their
-    // rows outside (diagonal ghosts) are clamped to stay in bounds and are
-    // never used.  Corner rows are clamped separately so that row 0 still
-    // sees corner row 0 as its south side.
-    float cs0, cs1;
-    {
-        int rc = xin ? y0 - 2 : min(max(y0 - 2, 0), ny);
-        cs0 = corner(d, il, rc);
-        cs1 = corner(d, il + 1, rc);
-    }
-    auto load = [&](Row &R, int r) {
-        int rr = xin ? r : min(max(r, 0), ny - 1);
-        int rc = xin ? r + 1 : min(max(r + 1, 0), ny);
-        CellIn ci = load_cell<PROJ>(d, E, U, V, il, rr, c.bk, c.bs);
-        R.e = ci.e; R.u = ci.u; R.v = ci.v; R.f = ci.f;
-        float cn0 = corner(d, il, rc), cn1 = corner(d, il + 1, rc);
-        row_terms<PROJ>(R, cs0, cs1, cn0, cn1, ci.th, d);
-        cs0 = cn0;
-        cs1 = cn1;
-    };
-
-    Row A, B, C;
-    F3 Gs = {0.f, 0.f, 0.f};
-    for (int k = y0 - 2; k <= y1 + 1; ++k) {
-        load(C, k);
-        if (k >= y0 - 1) y_diff(C, B, d);
-        if (k >= y0) {
-            float uS, vS;
-            y_faces(B, C, A.land, d, uS, vS);
-            F3 Gn = {0.f, 0.f, 0.f};
-            if (k >= y0 + 1) Gn = y_flux(A, B, uS, vS, d);
-            if (k >= y0 + 2) {
-                c.o = k - 2;
-                float e0 = 0.f, u0 = 0.f, v0 = 0.f;
-                if (STAGE == 2 && c.out_lane) {
-                    const size_t oq = (size_t)c.o * d.pitch + c.i;
-                    e0 = d.eta[oq]; u0 = d.hu[oq]; v0 = d.hv[oq];
-                }
-                finish_row<STAGE, PROJ, true>(A, Gs, Gn, c, e0, u0, v0, d, wmax_loc, bad);
-            }
-            Gs = Gn;
-        }
-        A = B;
-        B = C;
     }
 }
 
@@ -581,12 +638,14 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Ti
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
-    // Blocks are dispatched round-robin over the 8 XCDs: give each XCD a
-    // contiguous range of tiles so vertically adjacent tiles (which share
-    // halo rows) meet in the same L2.
+    // Blocks are dispatched round-robin over the 8 XCDs.  Order bit 1 clear:
+    // give each XCD a contiguous range of tiles so neighbouring tiles (which
+    // share halo rows) meet in the same L2.  Order bit 0: tiles numbered
+    // row-block-major (strips fastest), which spreads the edge strips over
+    // all compute units, instead of strip-major.
     const int nb = gridDim.x, b = blockIdx.x;
     const int q8 = nb >> 3, r8 = nb & 7, x8 = b & 7;
-    const int L = x8 * q8 + min(x8, r8) + (b >> 3);
+    const int L = (T.order & 2) ? b : x8 * q8 + min(x8, r8) + (b >> 3);
     const int tile = L * kWavesPerBlock + wid;
 
     Ctrl *ctrl = d.ctrl;
@@ -624,27 +683,33 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Ti
     wind_at(d, tau, c.wx, c.wy);
 
     const int nx = d.nx, ny = d.ny;
-    const int strip = tile / T.nrb, rb = tile - strip * T.nrb;
+    int strip, rb;
+    if (T.order & 1) { rb = tile / T.nstrips; strip = tile - rb * T.nstrips; }
+    else { strip = tile / T.nrb; rb = tile - strip * T.nrb; }
     const int x0 = strip * kStrip;
     const int y0 = rb * T.by, y1 = min(y0 + T.by, ny);
     c.i = x0 - kHalo + lane;
     c.o = y0;
     c.out_lane = lane >= kHalo && lane < kWave - kHalo && c.i < nx;
 
-    // interior: columns x0-2 .. x0+61 and rows y0-2 .. y1+2 (corner rows) inside
-    // the domain, and no output cell within the relaxation zone of a nested side
+    // ghost: some of columns x0-2 .. x0+61, rows y0-2 .. y1+1 or corner rows
+    // up to y1+2 fall outside the domain.  frs: some output cell lies within
+    // the relaxation zone of a nested side.
+    const bool ghost = !(x0 >= kHalo && x0 + kStrip + kHalo <= nx && y0 >= kHalo && y1 + kHalo <= ny);
     const int W = d.frs_w;
-    bool interior = x0 >= kHalo && x0 + kStrip + kHalo <= nx && y0 >= kHalo && y1 + kHalo <= ny - 1;
+    bool frs = false;
     if (W > 0) {
-        if (d.bc[0] == BC_NESTED && x0 < W) interior = false;
-        if (d.bc[1] == BC_NESTED && x0 + kStrip > nx - W) interior = false;
-        if (d.bc[2] == BC_NESTED && y0 < W) interior = false;
-        if (d.bc[3] == BC_NESTED && y1 > ny - W) interior = false;
+        frs |= d.bc[0] == BC_NESTED && x0 < W;
+        frs |= d.bc[1] == BC_NESTED && x0 + kStrip > nx - W;
+        frs |= d.bc[2] == BC_NESTED && y0 < W;
+        frs |= d.bc[3] == BC_NESTED && y1 > ny - W;
     }
     float wmax_loc = 0.f;
     int bad = 0;
-    if (interior) tile_interior<STAGE, PROJ>(d, c, y0, y1, wmax_loc, bad);
-    else tile_edge<STAGE, PROJ>(d, c, y0, y1, lane, wmax_loc, bad);
+    if (!ghost && !frs) run_tile<STAGE, PROJ, false, false>(d, c, y0, y1, wmax_loc, bad);
+    else if (!ghost) run_tile<STAGE, PROJ, false, true>(d, c, y0, y1, wmax_loc, bad);
+    else if (!frs) run_tile<STAGE, PROJ, true, false>(d, c, y0, y1, wmax_loc, bad);
+    else run_tile<STAGE, PROJ, true, true>(d, c, y0, y1, wmax_loc, bad);
 
     if (STAGE == 2) {
         wmax_loc = wave_max(wmax_loc);
@@ -799,6 +864,22 @@ hipError_t launch_stage(int stage, bool proj, const Dom &d, const Tiling &T, int
         }
     }
     return hipGetLastError();
+}
+
+// waves per SIMD that one stage kernel variant can keep resident, from its
+// register usage (512 VGPRs per SIMD lane on gfx950, 8-register granules)
+int stage_waves_per_simd(int stage, bool proj)
+{
+    hipFuncAttributes a{};
+    hipError_t e;
+    if (stage == 1) e = proj ? hipFuncGetAttributes(&a, (const void *)stage_kernel<1, true>)
+                             : hipFuncGetAttributes(&a, (const void *)stage_kernel<1, false>);
+    else e = proj ? hipFuncGetAttributes(&a, (const void *)stage_kernel<2, true>)
+                  : hipFuncGetAttributes(&a, (const void *)stage_kernel<2, false>);
+    if (e != hipSuccess || a.numRegs <= 0) return 3;
+    int regs = (a.numRegs + 7) / 8 * 8;
+    int w = 512 / regs;
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
 hipError_t launch_cfl(const Dom &d, int slot, hipStream_t s)

@@ -54,8 +54,8 @@ SIGNATURES = {
     "swe_set_state": (C.c_int, [_VP, _F, _F, _F, C.c_double]),
     "swe_diagnostics": (C.c_int, [_VP, _D, _D]),
     "swe_status": (C.c_int, [_VP]),
-    "swe_set_tiling": (C.c_int, [_VP, C.c_int32]),
-    "swe_get_tiling": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "swe_set_tiling": (C.c_int, [_VP, C.c_int32, C.c_int32]),
+    "swe_get_tiling": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "swe_enable_timing": (C.c_int, [_VP, C.c_int32]),
     "swe_stage_times": (C.c_int, [_VP, _D, _D, C.POINTER(C.c_int64), C.c_int32]),
     "swe_destroy": (None, [_VP]),
@@ -226,13 +226,14 @@ class Domain:
     def status(self) -> int:
         return load_library().swe_status(self._h)
 
-    def set_tiling(self, rows_per_wave: int = 0):
-        _check(load_library().swe_set_tiling(self._h, int(rows_per_wave)))
+    def set_tiling(self, rows_per_wave: int = 0, order: int = -1):
+        _check(load_library().swe_set_tiling(self._h, int(rows_per_wave), int(order)))
 
     def tiling(self):
-        by, w = C.c_int32(), C.c_int32()
-        _check(load_library().swe_get_tiling(self._h, C.byref(by), C.byref(w)))
-        return by.value, w.value
+        """(rows per wave, tile order, wavefronts per stage launch)"""
+        by, o, w = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(load_library().swe_get_tiling(self._h, C.byref(by), C.byref(o), C.byref(w)))
+        return by.value, o.value, w.value
 
     def enable_timing(self, on: bool = True):
         _check(load_library().swe_enable_timing(self._h, 1 if on else 0))

@@ -241,9 +241,9 @@ def test_tiling_does_not_change_results():
     wl = random_small(190, 97, seed=21, land_frac=0.15, bc=(BC_NESTED, BC_WALL, BC_PERIODIC, BC_PERIODIC),
                       friction=FRIC_MANNING, friction_coeff=0.03, wind=(0.1, -0.1))
     outs = []
-    for by in (0, 3, 7, 16, 64, 200):
+    for by, order in ((0, -1), (3, 0), (7, 1), (16, 2), (64, 3), (200, 1)):
         d = _dom(wl)
-        d.set_tiling(by)
+        d.set_tiling(by, order)
         d.step(20)
         outs.append((d.tiling(), d.read_state()))
         d.close()

@@ -175,6 +175,129 @@ int swe_stage_times(swe_domain *d, double *ms_stage1, double *ms_stage2, int64_t
 void swe_destroy(swe_domain *d);
 const char *swe_last_error(void);
 
+/* ---- batched ensemble ---------------------------------------------------
+ * Many domains of uneven sizes advanced together: each RK stage of all
+ * members is ONE persistent kernel launch that drains a device queue of
+ * (member, tile) work items (largest members first, split into 8
+ * partitions taken in chunks with one atomic each).  Every member keeps its
+ * own parameters, forcing, time and CFL time step (eq. cfl per member), so
+ * a member's result is bitwise the one it gets stepped alone.  Steps are
+ * replayed as captured HIP graphs.  Used for ensembles of perturbed runs and
+ * by the serving loop.  Members are borrowed; while they belong to the
+ * ensemble their own stepping calls return SWE_E_STATE and all their work
+ * (including swe_read_state) is ordered on the ensemble's stream. */
+typedef struct swe_ensemble swe_ensemble;
+
+/* Device workspace for an ensemble of these members with rows_per_wave rows
+ * per tile (0 = default) -- the member table, the work queue and its
+ * counters.  Errors: SWE_E_ARG. */
+int swe_ensemble_workspace_bytes(swe_domain *const *members, int32_t n, int32_t rows_per_wave, size_t *bytes);
+
+/* Group n >= 1 ready domains (boundary data set where nested; all with the
+ * same north_projection) into an ensemble using the caller's device workspace
+ * (256-byte aligned, borrowed until swe_ensemble_destroy) and stream.
+ * chunk = work items taken per atomic (0 = default 4).  Synchronises. */
+int swe_ensemble_create(swe_domain *const *members, int32_t n, void *dev_workspace, size_t bytes,
+                        void *hip_stream, int32_t rows_per_wave, int32_t chunk, swe_ensemble **out);
+
+/* Advance every member n_steps SSP-RK2 steps, each with its own dt.
+ * Asynchronous. */
+int swe_ensemble_step(swe_ensemble *e, int32_t n_steps);
+
+/* Reports the work decomposition (rows per tile, chunk, work items per
+ * stage, blocks of the persistent launch). */
+int swe_ensemble_info(swe_ensemble *e, int32_t *rows_per_wave, int32_t *chunk, int64_t *items, int32_t *blocks);
+
+/* HIP-event timing of the two ensemble stage kernels, as swe_stage_times. */
+int swe_ensemble_enable_timing(swe_ensemble *e, int32_t on);
+int swe_ensemble_stage_times(swe_ensemble *e, double *ms_stage1, double *ms_stage2, int64_t *launches,
+                             int32_t reset);
+
+/* on = 1 (default): swe_ensemble_step replays captured HIP graphs of 16
+ * steps; on = 0: every stage is launched directly (no capture cost, for
+ * ensembles that live only a few steps, as in the serving loop). */
+int swe_ensemble_use_graphs(swe_ensemble *e, int32_t on);
+
+/* Releases the ensemble; the members return to their own streams. */
+void swe_ensemble_destroy(swe_ensemble *e);
+
+/* ---- serving loop (continuous batching) ----------------------------------
+ * Forecast requests (a domain, its initial state and forcing, and a
+ * simulated-time horizon) arrive at any time; the server keeps the active
+ * ones resident in a caller-provided device arena and advances them together
+ * as one batched ensemble in ticks of a fixed number of SSP-RK2 steps.  At
+ * every tick boundary finished requests leave (their final state is copied
+ * to the caller's host buffers and their arena block is freed) and waiting
+ * requests join in arrival order while their HBM footprint (the
+ * swe_workspace_bytes of their domain) fits in the arena and an active slot
+ * is free.  Each request's last step is clamped so that it ends exactly at
+ * its horizon (the run-to-time rule of the scheme); a request's result is
+ * bitwise the one it gets when run alone.  Single-threaded: calls on one
+ * server must not overlap. */
+typedef struct swe_server swe_server;
+
+typedef struct swe_request {
+    int64_t id;           /* caller's tag, reported on completion */
+    swe_params params;    /* as for swe_init_domain */
+    double horizon;       /* simulated seconds to advance, >= 0 */
+    const float *Hc;      /* host inputs as for swe_init_domain; copied by swe_server_submit */
+    const uint8_t *land;  /* may be NULL */
+    const float *f;
+    const float *theta;   /* may be NULL */
+    const float *eta, *hu, *hv;
+    int32_t n_wind;       /* 0 = no wind, else n_wind times and (n_wind x 2) stresses, N/m^2 */
+    int32_t n_bnd;        /* boundary snapshots for nested sides (as swe_set_forcing), 0 if none */
+    const double *wind_t;
+    const float *wind_tau;
+    const double *bnd_t;
+    const float *bnd;
+    float *out_eta, *out_hu, *out_hv; /* host [ny][nx]; caller-owned, must stay valid until the
+                                         request is reported by swe_server_poll; may be NULL */
+} swe_request;
+
+typedef struct swe_completion {
+    int64_t id;
+    double t;        /* simulated time reached (= horizon unless status != SWE_OK) */
+    int64_t steps;   /* time steps taken */
+    int64_t tick;    /* tick after which it completed */
+    int32_t status;  /* SWE_OK or SWE_E_UNSTABLE (non-finite state; stopped early) */
+    int32_t pad;
+} swe_completion;
+
+typedef struct swe_server_stats {
+    int64_t submitted, admitted, completed, ticks;
+    int64_t cell_steps;             /* sum over requests of cells x steps taken so far */
+    size_t arena_bytes, arena_used, arena_peak;
+    int32_t active, pending;
+} swe_server_stats;
+
+/* dev_arena: caller-owned device memory (256-byte aligned) from which every
+ * admitted request's workspace and the ensemble's queue are carved.  Work
+ * runs on hip_stream; uploads of joining requests on upload_stream (may be
+ * the same), overlapping the running tick.  max_active >= 1;
+ * steps_per_tick >= 1; rows_per_wave / chunk as for the ensemble (0 =
+ * default).  Errors: SWE_E_ARG. */
+int swe_server_create(void *dev_arena, size_t arena_bytes, void *hip_stream, void *upload_stream, int32_t max_active,
+                      int32_t steps_per_tick, int32_t rows_per_wave, int32_t chunk, swe_server **out);
+
+/* Queue a request (inputs are validated and copied).  SWE_E_ARG for invalid
+ * inputs, SWE_E_NOMEM if its footprint exceeds the whole arena. */
+int swe_server_submit(swe_server *s, const swe_request *r);
+
+/* One tick: launch steps_per_tick steps of the active set, admit waiting
+ * requests (uploading them while the steps run), then retire the finished
+ * ones.  Synchronises.  Reports the active and waiting counts after the tick. */
+int swe_server_tick(swe_server *s, int32_t *n_active, int32_t *n_pending);
+
+/* Pops up to max completions (oldest first) into out; *n = number written. */
+int swe_server_poll(swe_server *s, swe_completion *out, int32_t max, int32_t *n);
+
+/* Counters of the server (requests, ticks, cell-steps, arena use). */
+int swe_server_get_stats(swe_server *s, swe_server_stats *st);
+
+/* Drops every active and waiting request and frees the server. */
+void swe_server_destroy(swe_server *s);
+
 #ifdef __cplusplus
 }
 #endif

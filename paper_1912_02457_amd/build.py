@@ -4,7 +4,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["csrc/swe_kernels.hip", "csrc/swe_api.hip"]
+SOURCES = ["csrc/swe_kernels.hip", "csrc/swe_api.hip", "csrc/swe_ensemble.hip", "csrc/swe_server.hip"]
 LIB = os.path.join(HERE, "lib", "libswe_hip.so")
 ARCH = os.environ.get("SWE_OFFLOAD_ARCH", "gfx950")
 

@@ -9,18 +9,7 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/swe.h"
-#include "swe_device.h"
-
-namespace swe {
-hipError_t launch_stage(int stage, bool proj, const Dom &d, const Tiling &T, int parity, double dt_fixed,
-                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
-hipError_t launch_cfl(const Dom &d, int slot, hipStream_t s);
-hipError_t launch_ctrl_reset(Ctrl *c, double t, int slot, hipStream_t s);
-hipError_t launch_set_t_end(Ctrl *c, double te, hipStream_t s);
-hipError_t launch_diagnostics(const Dom &d, hipStream_t s);
-int stage_waves_per_simd(int stage, bool proj);
-}  // namespace swe
+#include "swe_host.h"
 
 using namespace swe;
 
@@ -48,11 +37,6 @@ int hip_fail(hipError_t e, const char *what)
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int pitch_of(int n) { return (int)align_up((size_t)n, 64); }
-
-struct Layout {
-    size_t eta, hu, hv, eta1, hu1, hv1, Hc, f, north, fghost, nghost, alpha, bnd_t, bnd, wind_t, wind,
-        ctrl, partials, total;
-};
 
 Layout make_layout(const swe_params &p, int max_wind, int max_bnd)
 {
@@ -123,26 +107,7 @@ bool any_nested(const swe_params &p)
 
 }  // namespace
 
-struct swe_domain {
-    swe_params p{};
-    hipStream_t stream = nullptr;
-    hipStream_t capture_stream = nullptr;
-    char *ws = nullptr;
-    Layout L{};
-    Dom dom{};
-    Tiling T[2]{};  // per stage
-    int wps[2] = {3, 3};  // resident waves per SIMD of each stage kernel
-    int parity = 0;
-    int max_wind = 0, max_bnd = 0;
-    bool has_bnd = false;
-    std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (steps, start parity)
-    std::vector<hipGraph_t> graph_objs;
-    bool timing = false;
-    std::vector<hipEvent_t> ev_pool;
-    size_t ev_used = 0;
-    int64_t timed_steps = 0;
-    int cus = 256;
-};
+int swe::set_error(int code, const std::string &msg) { return fail(code, msg); }
 
 namespace {
 
@@ -193,6 +158,7 @@ int copy_state_to_star(swe_domain *d)
 int check_ready(swe_domain *d)
 {
     if (!d) return fail(SWE_E_ARG, "domain is NULL");
+    if (d->ensemble) return fail(SWE_E_STATE, "domain belongs to an ensemble: step the ensemble");
     if (any_nested(d->p) && !d->has_bnd) return fail(SWE_E_STATE, "nested boundary without boundary data");
     return SWE_OK;
 }
@@ -394,6 +360,7 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
 int swe_set_forcing(swe_domain *d, int32_t kind, int32_t n_times, const double *times, const float *data)
 {
     if (!d || !times || !data || n_times < 1) return fail(SWE_E_ARG, "bad forcing arguments");
+    if (d->ensemble) return fail(SWE_E_STATE, "domain belongs to an ensemble");
     for (int k = 0; k < n_times; ++k) {
         if (!std::isfinite(times[k])) return fail(SWE_E_ARG, "non-finite forcing time");
         if (k > 0 && !(times[k] > times[k - 1])) return fail(SWE_E_ARG, "forcing times must increase");
@@ -522,6 +489,7 @@ int swe_read_state(swe_domain *d, float *eta, float *hu, float *hv, double *t, d
 int swe_set_state(swe_domain *d, const float *eta, const float *hu, const float *hv, double t)
 {
     if (!d || !eta || !hu || !hv) return fail(SWE_E_ARG, "NULL argument");
+    if (d->ensemble) return fail(SWE_E_STATE, "domain belongs to an ensemble");
     const int nx = d->p.nx, ny = d->p.ny;
     size_t nc = (size_t)nx * ny;
     if (!std::isfinite(t) || !all_finite(eta, nc) || !all_finite(hu, nc) || !all_finite(hv, nc))
@@ -560,6 +528,7 @@ int swe_status(swe_domain *d)
 int swe_set_tiling(swe_domain *d, int32_t rows_per_wave, int32_t order)
 {
     if (!d) return fail(SWE_E_ARG, "domain is NULL");
+    if (d->ensemble) return fail(SWE_E_STATE, "domain belongs to an ensemble");
     if (rows_per_wave < 0 || rows_per_wave > 4096) return fail(SWE_E_ARG, "rows_per_wave out of range");
     if (order < -1 || order > 3) return fail(SWE_E_ARG, "order must be -1 (default) or 0..3");
     for (int st = 0; st < 2; ++st) {
@@ -617,6 +586,7 @@ void swe_destroy(swe_domain *d)
 {
     if (!d) return;
     if (d->stream) (void)hipStreamSynchronize(d->stream);
+    if (d->ensemble) ensemble_forget(d->ensemble, d);
     for (auto &kv : d->graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto g : d->graph_objs) (void)hipGraphDestroy(g);
     for (auto e : d->ev_pool) (void)hipEventDestroy(e);

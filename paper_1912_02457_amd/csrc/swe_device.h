@@ -121,4 +121,25 @@ inline Tiling make_tiling(int nx, int ny, int by)
     return t;
 }
 
+// ---- ensemble: many domains in one launch per stage ------------------------
+constexpr int kEnsParts = 8;  // queue partitions (blocks b with b % 8 == k drain part k)
+
+struct EnsMember {
+    Dom d;
+    Tiling T;
+    int pflip;  // this member's step parity = ensemble parity ^ pflip
+    int pad[3];
+};
+
+struct EnsItem {
+    int member;
+    int tile;
+};
+
+struct EnsCtrl {
+    uint32_t head[2][2][kEnsParts][32];  // [stage][parity][part], one 128-byte line each
+    uint32_t part_begin[kEnsParts];
+    uint32_t part_len[kEnsParts];
+};
+
 }  // namespace swe

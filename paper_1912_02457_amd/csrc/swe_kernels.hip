@@ -196,8 +196,12 @@ __device__ __forceinline__ F3 cu_flux(float eL, float pL0, float qL0, float eR, 
     float Hn = fminf(Hf, 0.f), Hs2 = Hf + fmaxf(Hf, 0.f);
     float PL = 0.5f * d.g * (eL + Hn) * (eL + Hs2), PR = 0.5f * d.g * (eR + Hn) * (eR + Hs2);
     float FL = fmaf(pL, uL, PL), FR = fmaf(pR, uR, PR);
+    // a+ - a- below 2^-100 m/s counts as a+ = a- = 0: its FP32 reciprocal
+    // would overflow (a denormal momentum on a dry face gives such speeds)
+    // and turn the weights into inf * 0.  Only faces with h_f <= 1e-61 m on
+    // both sides fall in the gap, where both branches agree to O(g h_f^2).
     float den = ap - am;
-    bool wet = den > 0.f;
+    bool wet = den > 0x1p-100f;
     float w = wet ? rcp(den) : 0.f;
     float al = wet ? ap * w : 0.5f;
     float be = 1.f - al;
@@ -625,58 +629,63 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
 }
 
 // ---------------------------------------------------------------------------
-// stage kernel
+// time step of one domain (the same in both stage kernels of a step and in
+// every wave): dt from the CFL accumulator of the step's parity (eq. cfl) or a
+// given dt, clamped to land on t_end, or the step skipped once t_end is reached
+// ---------------------------------------------------------------------------
+struct StepTime {
+    double tn, dtd;
+    uint32_t wbits;
+    bool skip, last;
+};
+
+__device__ __forceinline__ StepTime step_time(const Dom &d, int parity, double dt_fixed, int lane)
+{
+    const Ctrl *ctrl = d.ctrl;
+    StepTime s;
+    s.tn = ctrl->t[parity];
+    s.wbits = read_wmax(ctrl, parity, lane);
+    const double te = ctrl->t_end;
+    s.dtd = dt_fixed > 0.0 ? dt_fixed : (double)(d.courant_q / __uint_as_float(s.wbits));
+    s.skip = false;
+    s.last = false;
+    if (te > 0.0) {
+        if (s.tn >= te) s.skip = true;
+        else if (s.dtd >= te - s.tn) { s.dtd = te - s.tn; s.last = true; }
+    }
+    return s;
+}
+
+// Done by one wavefront per domain in stage 1: the slots of the next parity
+// are cleared for stage 2 to accumulate into (or, for a step past t_end, get
+// the current maximum), and the next time is published.
+__device__ __forceinline__ void advance_ctrl(Ctrl *ctrl, const StepTime &s, int parity, int lane)
+{
+    if (lane < kCflSlots) ctrl->wslot[parity ^ 1][lane][0] = s.skip ? s.wbits : 0u;
+    if (lane == 0) {
+        if (s.skip) {
+            ctrl->t[parity ^ 1] = s.tn;
+        } else {
+            ctrl->t[parity ^ 1] = s.last ? ctrl->t_end : s.tn + s.dtd;
+            ctrl->dt_last = (float)s.dtd;
+            ctrl->steps += 1;
+        }
+    }
+}
+
+// One tile (wavefront) of one stage:
 //   STAGE 1: Q* = (Q^n + dt M(Q^n)) / (1 + dt S(Q^n))               (momenta)
 //   STAGE 2: Q^{n+1} = (Q^n + Q* + dt M(Q*)) / 2 / (1 + dt/2 S(Q*))  (momenta)
 //            then flow relaxation (eq. frs) and the CFL reduction for the
 //            next step (eq. cfl)
 // eq. rk2_semiimp; M is eq. sw_semidiscrete with the sources of eq. swe.
-// ---------------------------------------------------------------------------
 template <int STAGE, bool PROJ>
-__global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Tiling T, int parity,
-                                                                      double dt_fixed)
+__device__ __forceinline__ void process_tile(const Dom &d, const Tiling &T, int tile, int parity, const StepTime &st,
+                                             int lane)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
-    // Blocks are dispatched round-robin over the 8 XCDs.  Order bit 1 clear:
-    // give each XCD a contiguous range of tiles so neighbouring tiles (which
-    // share halo rows) meet in the same L2.  Order bit 0: tiles numbered
-    // row-block-major (strips fastest), which spreads the edge strips over
-    // all compute units, instead of strip-major.
-    const int nb = gridDim.x, b = blockIdx.x;
-    const int q8 = nb >> 3, r8 = nb & 7, x8 = b & 7;
-    const int L = (T.order & 2) ? b : x8 * q8 + min(x8, r8) + (b >> 3);
-    const int tile = L * kWavesPerBlock + wid;
-
-    Ctrl *ctrl = d.ctrl;
-    const double tn = ctrl->t[parity];
-    const uint32_t wbits = read_wmax(ctrl, parity, lane);
-    const double te = ctrl->t_end;
-    double dtd = dt_fixed > 0.0 ? dt_fixed : (double)(d.courant_q / __uint_as_float(wbits));
-    bool skip = false, last = false;
-    if (te > 0.0) {
-        if (tn >= te) skip = true;
-        else if (dtd >= te - tn) { dtd = te - tn; last = true; }
-    }
-    if (STAGE == 1 && b == 0 && threadIdx.x < kCflSlots) {
-        // slots of the next parity: cleared for stage 2 to accumulate into, or,
-        // for a step past t_end, the current maximum carried over
-        ctrl->wslot[parity ^ 1][threadIdx.x][0] = skip ? wbits : 0u;
-        if (threadIdx.x == 0) {
-            if (skip) {
-                ctrl->t[parity ^ 1] = tn;
-            } else {
-                ctrl->t[parity ^ 1] = last ? te : tn + dtd;
-                ctrl->dt_last = (float)dtd;
-                ctrl->steps += 1;
-            }
-        }
-    }
-    if (skip || tile >= T.ntiles) return;
-
-    const double tau = STAGE == 1 ? tn : tn + dtd;
+    const double tau = STAGE == 1 ? st.tn : st.tn + st.dtd;
     TileCtx c;
-    c.dt = (float)dtd;
+    c.dt = (float)st.dtd;
     c.bk = 0;
     c.bs = 0.0;
     if (d.nb > 0) time_weights(d.nb, d.bnd_t, tau, c.bk, c.bs);
@@ -715,8 +724,72 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Ti
         wmax_loc = wave_max(wmax_loc);
         unsigned long long anybad = __ballot(bad);
         if (lane == 0) {
-            atomicMax(&ctrl->wslot[parity ^ 1][tile & (kCflSlots - 1)][0], __float_as_uint(wmax_loc));
-            if (anybad) atomicOr(&ctrl->flags, 1u);
+            atomicMax(&d.ctrl->wslot[parity ^ 1][tile & (kCflSlots - 1)][0], __float_as_uint(wmax_loc));
+            if (anybad) atomicOr(&d.ctrl->flags, 1u);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// single-domain stage kernel: one wavefront per tile
+// ---------------------------------------------------------------------------
+template <int STAGE, bool PROJ>
+__global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Tiling T, int parity,
+                                                                      double dt_fixed)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    // Blocks are dispatched round-robin over the 8 XCDs.  Order bit 1 clear:
+    // give each XCD a contiguous range of tiles so neighbouring tiles (which
+    // share halo rows) meet in the same L2.  Order bit 0: tiles numbered
+    // row-block-major (strips fastest) instead of strip-major.
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int q8 = nb >> 3, r8 = nb & 7, x8 = b & 7;
+    const int L = (T.order & 2) ? b : x8 * q8 + min(x8, r8) + (b >> 3);
+    const int tile = L * kWavesPerBlock + wid;
+
+    const StepTime st = step_time(d, parity, dt_fixed, lane);
+    if (STAGE == 1 && b == 0 && wid == 0) advance_ctrl(d.ctrl, st, parity, lane);
+    if (st.skip || tile >= T.ntiles) return;
+    process_tile<STAGE, PROJ>(d, T, tile, parity, st, lane);
+}
+
+// ---------------------------------------------------------------------------
+// ensemble stage kernel: many domains of uneven sizes in one persistent
+// launch.  The work items (member, tile) sit in a device queue split into 8
+// partitions; the waves of the blocks b with b % 8 == k drain partition k in
+// chunks taken with one atomicAdd each, until the partition is exhausted.
+// Every member has its own parameters, time, dt slot and CFL accumulator.
+// ---------------------------------------------------------------------------
+template <int STAGE, bool PROJ>
+__global__ __launch_bounds__(kWave * kWavesPerBlock) void ensemble_kernel(const EnsMember *__restrict__ mem,
+                                                                         const EnsItem *__restrict__ items,
+                                                                         EnsCtrl *ec, int parity, int chunk)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int part = blockIdx.x & (kEnsParts - 1);
+    // reset the queue heads the next kernel of the step sequence will use:
+    // stage 1 of parity p clears stage 2 of parity p, stage 2 clears stage 1
+    // of parity p^1 (neither is in use while this kernel runs)
+    if (blockIdx.x == 0 && threadIdx.x < kEnsParts) {
+        if (STAGE == 1) ec->head[1][parity][threadIdx.x][0] = 0u;
+        else ec->head[0][parity ^ 1][threadIdx.x][0] = 0u;
+    }
+    const uint32_t begin = ec->part_begin[part], len = ec->part_len[part];
+    uint32_t *head = &ec->head[STAGE - 1][parity][part][0];
+    while (true) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(head, (uint32_t)chunk);
+        base = __builtin_amdgcn_readfirstlane(base);
+        if (base >= len) break;
+        const uint32_t end = min(base + (uint32_t)chunk, len);
+        for (uint32_t j = base; j < end; ++j) {
+            const EnsItem it = items[begin + j];
+            const EnsMember &M = mem[it.member];
+            const int p = parity ^ M.pflip;
+            const StepTime st = step_time(M.d, p, 0.0, lane);
+            if (STAGE == 1 && it.tile == 0) advance_ctrl(M.d.ctrl, st, p, lane);
+            if (!st.skip) process_tile<STAGE, PROJ>(M.d, M.T, it.tile, p, st, lane);
         }
     }
 }
@@ -876,6 +949,44 @@ int stage_waves_per_simd(int stage, bool proj)
                              : hipFuncGetAttributes(&a, (const void *)stage_kernel<1, false>);
     else e = proj ? hipFuncGetAttributes(&a, (const void *)stage_kernel<2, true>)
                   : hipFuncGetAttributes(&a, (const void *)stage_kernel<2, false>);
+    if (e != hipSuccess || a.numRegs <= 0) return 3;
+    int regs = (a.numRegs + 7) / 8 * 8;
+    int w = 512 / regs;
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
+hipError_t launch_ensemble(int stage, bool proj, const EnsMember *mem, const EnsItem *items, EnsCtrl *ec,
+                           int parity, int chunk, int nblocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    dim3 grid(nblocks), block(kWave * kWavesPerBlock);
+    if (ev0) {
+        if (stage == 1) {
+            if (proj) hipExtLaunchKernelGGL(ensemble_kernel<1, true>, grid, block, 0, s, ev0, ev1, 0, mem, items, ec, parity, chunk);
+            else hipExtLaunchKernelGGL(ensemble_kernel<1, false>, grid, block, 0, s, ev0, ev1, 0, mem, items, ec, parity, chunk);
+        } else {
+            if (proj) hipExtLaunchKernelGGL(ensemble_kernel<2, true>, grid, block, 0, s, ev0, ev1, 0, mem, items, ec, parity, chunk);
+            else hipExtLaunchKernelGGL(ensemble_kernel<2, false>, grid, block, 0, s, ev0, ev1, 0, mem, items, ec, parity, chunk);
+        }
+    } else {
+        if (stage == 1) {
+            if (proj) ensemble_kernel<1, true><<<grid, block, 0, s>>>(mem, items, ec, parity, chunk);
+            else ensemble_kernel<1, false><<<grid, block, 0, s>>>(mem, items, ec, parity, chunk);
+        } else {
+            if (proj) ensemble_kernel<2, true><<<grid, block, 0, s>>>(mem, items, ec, parity, chunk);
+            else ensemble_kernel<2, false><<<grid, block, 0, s>>>(mem, items, ec, parity, chunk);
+        }
+    }
+    return hipGetLastError();
+}
+
+int ensemble_waves_per_simd(int stage, bool proj)
+{
+    hipFuncAttributes a{};
+    hipError_t e;
+    if (stage == 1) e = proj ? hipFuncGetAttributes(&a, (const void *)ensemble_kernel<1, true>)
+                             : hipFuncGetAttributes(&a, (const void *)ensemble_kernel<1, false>);
+    else e = proj ? hipFuncGetAttributes(&a, (const void *)ensemble_kernel<2, true>)
+                  : hipFuncGetAttributes(&a, (const void *)ensemble_kernel<2, false>);
     if (e != hipSuccess || a.numRegs <= 0) return 3;
     int regs = (a.numRegs + 7) / 8 * 8;
     int w = 512 / regs;

@@ -40,6 +40,30 @@ class Params(C.Structure):
     ]
 
 
+class Request(C.Structure):
+    _fields_ = [
+        ("id", C.c_int64), ("params", Params), ("horizon", C.c_double),
+        ("Hc", C.POINTER(C.c_float)), ("land", C.POINTER(C.c_uint8)), ("f", C.POINTER(C.c_float)),
+        ("theta", C.POINTER(C.c_float)), ("eta", C.POINTER(C.c_float)), ("hu", C.POINTER(C.c_float)),
+        ("hv", C.POINTER(C.c_float)), ("n_wind", C.c_int32), ("n_bnd", C.c_int32),
+        ("wind_t", C.POINTER(C.c_double)), ("wind_tau", C.POINTER(C.c_float)),
+        ("bnd_t", C.POINTER(C.c_double)), ("bnd", C.POINTER(C.c_float)),
+        ("out_eta", C.POINTER(C.c_float)), ("out_hu", C.POINTER(C.c_float)), ("out_hv", C.POINTER(C.c_float)),
+    ]
+
+
+class Completion(C.Structure):
+    _fields_ = [("id", C.c_int64), ("t", C.c_double), ("steps", C.c_int64), ("tick", C.c_int64),
+                ("status", C.c_int32), ("pad", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("ticks", C.c_int64), ("cell_steps", C.c_int64), ("arena_bytes", C.c_size_t),
+                ("arena_used", C.c_size_t), ("arena_peak", C.c_size_t), ("active", C.c_int32),
+                ("pending", C.c_int32)]
+
+
 # exported symbols of include/swe.h and their ctypes signatures
 _VP, _F, _D, _U8 = C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_uint8)
 SIGNATURES = {
@@ -60,6 +84,23 @@ SIGNATURES = {
     "swe_stage_times": (C.c_int, [_VP, _D, _D, C.POINTER(C.c_int64), C.c_int32]),
     "swe_destroy": (None, [_VP]),
     "swe_last_error": (C.c_char_p, []),
+    "swe_ensemble_workspace_bytes": (C.c_int, [C.POINTER(_VP), C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "swe_ensemble_create": (C.c_int, [C.POINTER(_VP), C.c_int32, _VP, C.c_size_t, _VP, C.c_int32, C.c_int32,
+                                      C.POINTER(_VP)]),
+    "swe_ensemble_step": (C.c_int, [_VP, C.c_int32]),
+    "swe_ensemble_info": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_int32)]),
+    "swe_ensemble_enable_timing": (C.c_int, [_VP, C.c_int32]),
+    "swe_ensemble_stage_times": (C.c_int, [_VP, _D, _D, C.POINTER(C.c_int64), C.c_int32]),
+    "swe_ensemble_use_graphs": (C.c_int, [_VP, C.c_int32]),
+    "swe_ensemble_destroy": (None, [_VP]),
+    "swe_server_create": (C.c_int, [_VP, C.c_size_t, _VP, _VP, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                    C.POINTER(_VP)]),
+    "swe_server_submit": (C.c_int, [_VP, C.c_void_p]),
+    "swe_server_tick": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "swe_server_poll": (C.c_int, [_VP, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "swe_server_get_stats": (C.c_int, [_VP, C.c_void_p]),
+    "swe_server_destroy": (None, [_VP]),
 }
 
 _lib = None
@@ -247,6 +288,172 @@ class Domain:
         if getattr(self, "_h", None):
             load_library().swe_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ensemble:
+    """Domains advanced together: one persistent launch per RK stage drains a
+    device queue of (member, tile) items over all members.  Each member keeps
+    its own time step; members stay usable for read_state / diagnostics and
+    return to their own streams on close()."""
+
+    def __init__(self, members: Sequence[Domain], *, rows_per_wave: int = 0, chunk: int = 0, stream=None):
+        import torch
+        L = load_library()
+        if not members:
+            raise ValueError("an ensemble needs at least one member")
+        self.members = list(members)
+        dev = self.members[0].device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        n = len(self.members)
+        arr = (_VP * n)(*[m._h for m in self.members])
+        nb = C.c_size_t()
+        _check(L.swe_ensemble_workspace_bytes(arr, n, int(rows_per_wave), C.byref(nb)))
+        self.workspace = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=dev)
+        h = C.c_void_p()
+        _check(L.swe_ensemble_create(arr, n, C.c_void_p(self.workspace.data_ptr()), nb.value,
+                                     C.c_void_p(self.stream.cuda_stream), int(rows_per_wave), int(chunk),
+                                     C.byref(h)))
+        self._h = h
+
+    def step(self, n: int = 1):
+        _check(load_library().swe_ensemble_step(self._h, int(n)))
+
+    def use_graphs(self, on: bool = True):
+        _check(load_library().swe_ensemble_use_graphs(self._h, 1 if on else 0))
+
+    def info(self):
+        """(rows per tile, items per atomic, work items per stage, blocks per launch)"""
+        r, c, i, b = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int32()
+        _check(load_library().swe_ensemble_info(self._h, C.byref(r), C.byref(c), C.byref(i), C.byref(b)))
+        return r.value, c.value, i.value, b.value
+
+    def enable_timing(self, on: bool = True):
+        _check(load_library().swe_ensemble_enable_timing(self._h, 1 if on else 0))
+
+    def stage_times(self, reset: bool = True):
+        a, b, n = C.c_double(), C.c_double(), C.c_int64()
+        _check(load_library().swe_ensemble_stage_times(self._h, C.byref(a), C.byref(b), C.byref(n),
+                                                       1 if reset else 0))
+        return a.value, b.value, n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().swe_ensemble_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def params_of(wl, north_projection=False) -> Params:
+    return make_params(wl.nx, wl.ny, wl.dx, wl.dy, g=wl.g, courant=wl.courant, theta=wl.theta,
+                       kappa=wl.kappa, bc=wl.bc, friction=wl.friction, friction_coeff=wl.friction_coeff,
+                       rho_w=wl.rho_w, frs_width=wl.frs_width, frs_d0=wl.frs_d0,
+                       north_projection=north_projection)
+
+
+class Server:
+    """Continuous-batching serving loop over one device arena (a torch
+    uint8 tensor of ``arena_bytes``): submit requests at any time, call
+    tick() repeatedly, poll() the finished ones with their final state."""
+
+    def __init__(self, arena_bytes: int, *, max_active: int = 64, steps_per_tick: int = 32,
+                 rows_per_wave: int = 0, chunk: int = 0, device=None, stream=None, upload_stream=None):
+        import torch
+        L = load_library()
+        self.device = torch.device(device if device is not None else "cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.upload_stream = upload_stream if upload_stream is not None else torch.cuda.Stream(self.device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        _check(L.swe_server_create(C.c_void_p(self.arena.data_ptr()), int(arena_bytes),
+                                   C.c_void_p(self.stream.cuda_stream),
+                                   C.c_void_p(self.upload_stream.cuda_stream), int(max_active),
+                                   int(steps_per_tick), int(rows_per_wave), int(chunk), C.byref(h)))
+        self._h = h
+        self._out = {}  # id -> host result arrays, alive until polled
+
+    def submit(self, wl, horizon: float, req_id: int, *, keep_result: bool = True):
+        """Queue workload ``wl`` to be advanced to simulated time ``horizon``."""
+        ny, nx = wl.ny, wl.nx
+        r = Request()
+        r.id = int(req_id)
+        r.params = params_of(wl)
+        r.horizon = float(horizon)
+        Hc = _f32(wl.Hc, (ny + 1, nx + 1))
+        f = _f32(wl.f, (ny, nx))
+        eta, hu, hv = (_f32(a, (ny, nx)) for a in (wl.eta, wl.hu, wl.hv))
+        north = None if wl.north is None else _f32(wl.north, (ny, nx))
+        land = None if wl.land is None else np.ascontiguousarray(np.asarray(wl.land, dtype=np.uint8))
+        r.Hc, r.f, r.eta, r.hu, r.hv = _fp(Hc), _fp(f), _fp(eta), _fp(hu), _fp(hv)
+        r.theta = _fp(north)
+        if land is not None:
+            r.land = land.ctypes.data_as(_U8)
+        wt = np.ascontiguousarray(np.asarray(wl.wind_t, dtype=np.float64))
+        wtau = _f32(wl.wind_tau, (len(wt), 2))
+        r.n_wind = len(wt)
+        r.wind_t, r.wind_tau = wt.ctypes.data_as(_D), _fp(wtau)
+        if wl.bnd is not None:
+            bt = np.ascontiguousarray(np.asarray(wl.bnd_t, dtype=np.float64))
+            bd = _f32(wl.bnd, (len(bt), 3, 2 * ny + 2 * nx))
+            r.n_bnd = len(bt)
+            r.bnd_t, r.bnd = bt.ctypes.data_as(_D), _fp(bd)
+        out = None
+        if keep_result:
+            out = tuple(np.empty((ny, nx), np.float32) for _ in range(3))
+            r.out_eta, r.out_hu, r.out_hv = (_fp(a) for a in out)
+        _check(load_library().swe_server_submit(self._h, C.addressof(r)))
+        self._out[int(req_id)] = out
+
+    def tick(self):
+        """One tick; returns (active, waiting) request counts."""
+        a, p = C.c_int32(), C.c_int32()
+        _check(load_library().swe_server_tick(self._h, C.byref(a), C.byref(p)))
+        return a.value, p.value
+
+    def poll(self, max_n: int = 4096):
+        """Finished requests: list of dicts with id, t, steps, tick, status
+        and the final (eta, hu, hv) host arrays (or None)."""
+        buf = (Completion * max_n)()
+        n = C.c_int32()
+        _check(load_library().swe_server_poll(self._h, C.addressof(buf), max_n, C.byref(n)))
+        res = []
+        for k in range(n.value):
+            c = buf[k]
+            res.append(dict(id=c.id, t=c.t, steps=c.steps, tick=c.tick, status=c.status,
+                            state=self._out.pop(c.id, None)))
+        return res
+
+    def stats(self):
+        st = ServerStats()
+        _check(load_library().swe_server_get_stats(self._h, C.addressof(st)))
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().swe_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:

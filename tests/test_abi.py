@@ -125,6 +125,23 @@ def test_null_handles_rejected(lib):
     lib.swe_destroy(None)
 
 
+def test_ensemble_arguments_rejected_without_gpu(lib):
+    import ctypes as C
+    from paper_1912_02457_amd import swe
+    n = C.c_size_t()
+    assert lib.swe_ensemble_workspace_bytes(None, 1, 0, C.byref(n)) == swe.SWE_E_ARG
+    empty = (C.c_void_p * 1)(None)
+    assert lib.swe_ensemble_workspace_bytes(empty, 1, 0, C.byref(n)) == swe.SWE_E_ARG
+    assert lib.swe_ensemble_workspace_bytes(empty, 0, 0, C.byref(n)) == swe.SWE_E_ARG
+    h = C.c_void_p()
+    assert lib.swe_ensemble_create(empty, 1, None, 0, None, 0, 0, C.byref(h)) == swe.SWE_E_ARG
+    assert lib.swe_ensemble_create(None, 0, None, 0, None, 0, 0, C.byref(h)) == swe.SWE_E_ARG
+    assert lib.swe_ensemble_step(None, 1) == swe.SWE_E_ARG
+    assert lib.swe_ensemble_info(None, None, None, None, None) == swe.SWE_E_ARG
+    assert lib.swe_ensemble_stage_times(None, None, None, None, 0) == swe.SWE_E_ARG
+    lib.swe_ensemble_destroy(None)
+
+
 def test_product_path_has_no_oracle_or_cpu_fallback():
     """The package never imports the oracle and has no numpy time stepping."""
     pkg = os.path.join(ROOT, "paper_1912_02457_amd")

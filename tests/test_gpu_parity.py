@@ -124,6 +124,25 @@ def test_full_size_first_steps(which):
     _say(which, p1, p2)
 
 
+def test_denormal_momenta_at_dry_front():
+    """Denormal momenta in the last wet cells before the beach's dry front
+    (the state a long run reaches as numerical diffusion creeps ahead of
+    the wave): the face between the last wet cell and the first dry one has
+    a denormal a+ - a-, whose FP32 reciprocal must not turn the flux into
+    inf * 0.  Stays finite and matches the oracle."""
+    wl = config3(nx=128, ny=16, steps=30)
+    hu = wl.hu.copy()
+    hu[:, 81:85] = np.float32(2.8e-45) * np.arange(1, 5, dtype=np.float32)
+    wl = wl.copy(hu=hu)
+    assert np.count_nonzero(hu) == 64 and hu.max() < 1e-43
+    _say("denormal dry front")
+    ref, t_ref, rep, own = run_both(wl, 30)
+    for a in own[:3]:
+        assert np.isfinite(a).all()
+    assert_parity(rep, ref, label="denormal front dt-replay")
+    assert_parity(own, ref, label="denormal front own-dt")
+
+
 def test_config3_runs_dry_front_stays_sane():
     """500 steps of the wet-dry beach: no NaN, depth non-negative up to the
     dry tolerance scale, incoming wave entered."""

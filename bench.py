@@ -5,30 +5,41 @@ latitude-dependent f), one MI355X.
 
 One "step" = both stage kernels of one SSP-RK2 step over the whole domain,
 with the time step computed on the device from the CFL condition.  Inputs are
-resident in HBM before the timed region starts.  Prints ONE JSON line.
+resident in HBM before the timed region starts.  Prints ONE JSON line; beside
+the headline figure it carries
+  "ensemble": 256 coastal members (200..1000 x 200..600 cells) advanced by
+              the persistent ensemble launch, against a per-domain loop;
+  "serving":  the continuous-batching server on Poisson arrivals of forecast
+              requests (time-scaled: horizons and inter-arrival times x0.1),
+              with p50/p99 latency next to throughput.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-ensemble] [--no-serving]
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-# Algorithmic bytes per cell and stage (float32 state; Coriolis-field plane
-# f carries the land mask; corner depths count one float per cell):
+# Algorithmic bytes per cell and stage (float32 state; the Coriolis-field
+# plane f carries the land mask; corner depths count one float per cell):
 #   stage 1, wet cell : read eta,hu,hv (12) + Hc (4) + f (4), write Q* (12)      = 32
 #   stage 2, wet cell : read Q* (12) + Q^n (12) + Hc (4) + f (4), write Q^n+1 (12) = 44
 #   land cell, either stage: read its Q (12) + Hc (4) + f (4) for the neighbours,
 #   nothing written (land is frozen)                                            = 20
 BYTES = {1: (32, 20), 2: (44, 20)}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_kernels_norkyst_2600x900.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1912_02457_amd", "csrc", "swe_kernels.hip")
 
 
 def parse():
@@ -38,8 +49,17 @@ def parse():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-members", type=int, default=256)
+    ap.add_argument("--ensemble-steps", type=int, default=500)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-time-scale", type=float, default=0.1,
+                    help="factor on horizons and inter-arrival times of the request stream")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run warmup + this many steps (for rocprofv3 runs), no JSON")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="with --profile-steps: also run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -68,20 +88,28 @@ def cpu_baseline(wl, target_s):
     }
 
 
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the shallow-water path here is a "
-              "single-GPU build and no multi-GPU figure is produced", file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
-    import torch
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (scaled by the copy-kernel calibration), or
+    None when the kernel source changed since they were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    src = hashlib.sha1(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha1") != src:
+        return None
+    key = f"{kernel}_hbm_bytes_per_launch"
+    return float(vals[key]) if key in vals else None
 
+
+def bench_single(a, np, torch):
     from paper_1912_02457_amd import Domain
     from workloads import config2
 
-    assert torch.cuda.is_available(), "bench needs a GPU"
-    torch.cuda.set_device(0)
     wl = config2()
     cells = wl.nx * wl.ny
     land_cells = int(np.count_nonzero(wl.land)) if wl.land is not None else 0
@@ -94,8 +122,15 @@ def main():
     if a.profile_steps:
         dom.step(a.profile_steps)
         torch.cuda.synchronize()
+        if a.copy_calibration:
+            x = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0").fill_(1.0)
+            y = torch.empty_like(x)
+            torch.cuda.synchronize()
+            for _ in range(3):
+                y.copy_(x)
+            torch.cuda.synchronize()
         print(f"profiled {a.profile_steps} steps", flush=True)
-        return
+        return None, wl
 
     # timed region: K steps through the captured HIP graphs of the stage
     # kernels (the production path), wall clock with a device sync on both sides
@@ -128,6 +163,7 @@ def main():
     ms_dom = ms2 if dominant == 2 else ms1
     bytes_dom = b2 if dominant == 2 else b1
     achieved = bytes_dom / (ms_dom * 1e-3) / 1e9
+    traffic = measured_traffic(f"stage{dominant}")
 
     value = cells * a.steps / el
     out = {
@@ -157,7 +193,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "algorithmic_bytes_per_launch": bytes_dom,
             "avg_launch_ms": ms_dom,
             "stage1_ms": ms1, "stage2_ms": ms2, "timed_launches": nl,
@@ -168,8 +204,189 @@ def main():
         "sim_time_s": t_sim,
         "state_finite": finite,
     }
+    return out, wl
+
+
+def _member(k):
+    from workloads import config4_member
+    return config4_member(k)
+
+
+def bench_ensemble(a, torch):
+    """256-member ensemble (coastal 1 km domains, walls, per-member wind),
+    each member with its own dt: aggregate cell-updates/s of the persistent
+    ensemble launch (autotuned tiles, graph replay) and of stepping the same
+    domains one after the other."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    from paper_1912_02457_amd import Domain, Ensemble
+    from paper_1912_02457_amd.tune import autotune_ensemble
+
+    n = a.ensemble_members
+    with ProcessPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        wls = list(ex.map(_member, range(n), chunksize=4))
+    cells = sum(w.nx * w.ny for w in wls)
+    # tile shape from a short sweep on throw-away copies of the members
+    probe = [Domain.from_workload(w, device="cuda:0") for w in wls]
+    rows, chunk, rep = autotune_ensemble(probe, steps=16)
+    for d in probe:
+        d.close()
+    del probe
+    doms = [Domain.from_workload(w, device="cuda:0") for w in wls]
+    torch.cuda.synchronize()
+    ens = Ensemble(doms, rows_per_wave=rows, chunk=chunk)
+    info = ens.info()
+    S = a.ensemble_steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.step(S)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ens.enable_timing(True)
+    ens.stage_times()
+    ens.step(32)
+    ms1, ms2, _ = ens.stage_times()
+    ens.close()
+    # baseline: the same members stepped one domain at a time (each through
+    # its own captured graphs)
+    L = 64
+    for d in doms:
+        d.step(16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d in doms:
+        d.step(L)
+    torch.cuda.synchronize()
+    el_loop = time.perf_counter() - t0
+    for d in doms:
+        d.close()
+    value = cells * S / el
+    loop = cells * L / el_loop
+    return {
+        "metric": "ensemble aggregate cell-updates/s",
+        "value": value,
+        "unit": "cell-updates/s",
+        "workload": f"{n} coastal members 200..1000 x 200..600 cells at 1 km, walls, f=1.2e-4, "
+                    "per-member wind, own dt each",
+        "members": n, "cells": cells, "steps": S, "ms_per_step": el / S * 1e3,
+        "rows_per_wave": rows, "chunk": chunk, "work_items": info[2], "blocks": info[3],
+        "stage1_ms": ms1, "stage2_ms": ms2,
+        "per_domain_loop_value": loop, "speedup_vs_loop": value / loop,
+        "autotune": {k: v for k, v in rep.items() if k != "trials"},
+    }
+
+
+def bench_serving(a, torch):
+    """Continuous batching of forecast requests (flat 100 m, walls,
+    f = 1.2e-4, Gaussian bump; sizes 100..2000 x 100..800) arriving as a
+    Poisson stream; horizons and inter-arrival times are scaled by
+    ``serve_time_scale`` so the offered load matches the full stream's.
+    Latency = completion minus arrival, wall clock."""
+    from collections import deque
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    from paper_1912_02457_amd import Server
+    from workloads import config5_requests
+    from workloads.configs import config5_member
+
+    sc = a.serve_time_scale
+    reqs = config5_requests()[: a.serve_requests]
+    arrivals = np.array([r["arrival"] for r in reqs]) * sc
+    horizons = [r["horizon"] * sc for r in reqs]
+    srv = Server(48 << 30, max_active=64, steps_per_tick=24, device="cuda:0")
+    done_at = {}
+    submitted = threading.Event()
+    errors = []
+
+    def feeder():
+        try:
+            with ThreadPoolExecutor(6) as ex:
+                window = deque()
+                nxt = 0
+                for k in range(len(reqs)):
+                    while nxt < len(reqs) and len(window) < 24:
+                        r = reqs[nxt]
+                        window.append(ex.submit(config5_member, r["nx"], r["ny"], 0.0))
+                        nxt += 1
+                    wl = window.popleft().result()
+                    wait = t0 + arrivals[k] - time.perf_counter()
+                    if wait > 0:
+                        time.sleep(wait)
+                    srv.submit(wl, horizons[k], req_id=k, keep_result=False)
+        except Exception as exc:  # surfaced by the main thread
+            errors.append(exc)
+        finally:
+            submitted.set()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th = threading.Thread(target=feeder, daemon=True)
+    th.start()
+    while True:
+        act, pend = srv.tick()
+        now = time.perf_counter()
+        for c in srv.poll():
+            done_at[c["id"]] = (now, c["status"], c["steps"])
+        if submitted.is_set() and act == 0 and pend == 0:
+            break
+        if act == 0 and pend == 0:
+            time.sleep(2e-4)
+    th.join()
+    if errors:
+        raise errors[0]
+    t_end = time.perf_counter()
+    st = srv.stats()
+    srv.close()
+    lat = np.array([done_at[k][0] - (t0 + arrivals[k]) for k in range(len(reqs))])
+    ok = sum(1 for v in done_at.values() if v[1] == 0)
+    cell_steps = st["cell_steps"]
+    span = t_end - t0
+    offered = sum(r["nx"] * r["ny"] * np.ceil(h / 3.59) for r, h in zip(reqs, horizons))
+    return {
+        "metric": "served cell-updates/s",
+        "value": cell_steps / span,
+        "unit": "cell-updates/s",
+        "workload": f"{len(reqs)} forecast requests, Poisson arrivals at {20.0 / sc:.0f}/s, "
+                    f"nx 100..2000 x ny 100..800 at 1 km, horizons U[1,24] h x {sc}",
+        "requests": len(reqs), "completed_ok": ok, "time_scale": sc,
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "max": float(lat.max()), "mean": float(lat.mean())},
+        "offered_cell_steps_per_s": float(offered / (arrivals[-1] - arrivals[0] + 1e-9)),
+        "span_s": span, "ticks": st["ticks"], "steps_per_tick": 24, "max_active": 64,
+        "arena_peak_GiB": st["arena_peak"] / 2**30,
+    }
+
+
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the shallow-water path here is a "
+              "single-GPU build and no multi-GPU figure is produced", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    out, wl = bench_single(a, np, torch)
+    if out is None:
+        return
+    _progress(f"single domain: {out['value']:.3e} cell-updates/s")
+    if not a.no_ensemble:
+        out["ensemble"] = bench_ensemble(a, torch)
+        _progress(f"ensemble: {out['ensemble']['value']:.3e} cell-updates/s")
+    if not a.no_serving:
+        out["serving"] = bench_serving(a, torch)
+        _progress(f"serving: p50 {out['serving']['latency_s']['p50']:.3f} s")
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds)
+        _progress("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

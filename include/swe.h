@@ -232,8 +232,9 @@ void swe_ensemble_destroy(swe_ensemble *e);
  * swe_workspace_bytes of their domain) fits in the arena and an active slot
  * is free.  Each request's last step is clamped so that it ends exactly at
  * its horizon (the run-to-time rule of the scheme); a request's result is
- * bitwise the one it gets when run alone.  Single-threaded: calls on one
- * server must not overlap. */
+ * bitwise the one it gets when run alone.  swe_server_submit may be called
+ * from another thread while a tick runs; no other calls on one server may
+ * overlap. */
 typedef struct swe_server swe_server;
 
 typedef struct swe_request {
@@ -260,7 +261,8 @@ typedef struct swe_completion {
     double t;        /* simulated time reached (= horizon unless status != SWE_OK) */
     int64_t steps;   /* time steps taken */
     int64_t tick;    /* tick after which it completed */
-    int32_t status;  /* SWE_OK or SWE_E_UNSTABLE (non-finite state; stopped early) */
+    int32_t status;  /* SWE_OK; SWE_E_UNSTABLE (non-finite state, stopped early); SWE_E_NOMEM
+                        (its workspace and work queue do not fit even in the empty arena) */
     int32_t pad;
 } swe_completion;
 

@@ -9,6 +9,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 
 #include "swe_host.h"
 
@@ -116,6 +117,7 @@ struct swe_server {
     Arena arena;
     hipStream_t stream = nullptr, upload = nullptr;
     int max_active = 1, steps_per_tick = 1, rows = 0, chunk = 0;
+    std::mutex qlock;  // guards pending and submitted (swe_server_submit may run beside a tick)
     std::deque<std::unique_ptr<Pending>> pending;
     std::vector<Active> active;
     std::deque<swe_completion> done;
@@ -207,6 +209,45 @@ std::vector<swe_domain *> active_domains(swe_server *s)
     return v;
 }
 
+// An idle server gives its work-queue blocks back, so that the arena is
+// whole for the next admission.
+void release_queue_blocks(swe_server *s)
+{
+    drop_ensemble(s);
+    if (s->ens_bytes) s->arena.release(s->ens_off, s->ens_bytes);
+    if (s->ens_new_bytes) s->arena.release(s->ens_new_off, s->ens_new_bytes);
+    s->ens_bytes = s->ens_new_bytes = 0;
+    s->dirty = false;
+}
+
+// The head of the queue does not fit even in an empty arena (its workspace
+// plus its work queue): it completes at once with SWE_E_NOMEM.
+int refuse_head(swe_server *s, std::unique_ptr<Pending> q)
+{
+    swe_completion c{};
+    c.id = q->r.id;
+    c.tick = s->ticks;
+    c.status = SWE_E_NOMEM;
+    s->done.push_back(c);
+    s->completed += 1;
+    return SWE_OK;
+}
+
+std::unique_ptr<Pending> pop_pending(swe_server *s)
+{
+    std::lock_guard<std::mutex> g(s->qlock);
+    if (s->pending.empty()) return nullptr;
+    auto q = std::move(s->pending.front());
+    s->pending.pop_front();
+    return q;
+}
+
+void push_back_front(swe_server *s, std::unique_ptr<Pending> q)
+{
+    std::lock_guard<std::mutex> g(s->qlock);
+    s->pending.push_front(std::move(q));
+}
+
 // Admit waiting requests in arrival order while a slot is free and both the
 // request's workspace and the (possibly grown) ensemble queue fit in the
 // arena.  Runs while the current tick's steps execute: nothing the running
@@ -216,10 +257,15 @@ int admit(swe_server *s)
 {
     std::vector<std::pair<int, int>> shapes;
     for (auto &a : s->active) shapes.emplace_back(a.dom->p.nx, a.dom->p.ny);
-    while (!s->pending.empty() && (int)s->active.size() < s->max_active) {
-        Pending *q = s->pending.front().get();
+    while ((int)s->active.size() < s->max_active) {
+        std::unique_ptr<Pending> q = pop_pending(s);
+        if (!q) break;
         size_t off;
-        if (!s->arena.alloc(q->bytes, &off)) break;
+        if (!s->arena.alloc(q->bytes, &off)) {
+            if (s->active.empty()) return refuse_head(s, std::move(q));  // could never start
+            push_back_front(s, std::move(q));
+            break;
+        }
         // the queue size depends only on the members' shapes
         shapes.emplace_back(q->r.params.nx, q->r.params.ny);
         const size_t need = ensemble_bytes_for_shapes(shapes, s->rows);
@@ -232,12 +278,14 @@ int admit(swe_server *s)
                 if (!s->arena.alloc(grow_bytes, &grow_off)) {
                     s->arena.release(off, q->bytes);
                     shapes.pop_back();
+                    if (s->active.empty()) return refuse_head(s, std::move(q));
+                    push_back_front(s, std::move(q));
                     break;
                 }
             }
         }
         swe_domain *d = nullptr;
-        int rc = start_request(s, q, off, &d);
+        int rc = start_request(s, q.get(), off, &d);
         if (rc) {
             s->arena.release(off, q->bytes);
             if (grow_bytes) s->arena.release(grow_off, grow_bytes);
@@ -249,11 +297,10 @@ int admit(swe_server *s)
             s->ens_new_bytes = grow_bytes;
         }
         Active a;
-        a.req = std::move(s->pending.front());
-        s->pending.pop_front();
+        a.bytes = q->bytes;
+        a.req = std::move(q);
         a.dom = d;
         a.off = off;
-        a.bytes = q->bytes;
         s->active.push_back(std::move(a));
         s->admitted += 1;
         s->dirty = true;
@@ -343,6 +390,7 @@ int swe_server_submit(swe_server *s, const swe_request *r)
     if (rc) return rc;
     if (align_up(q->bytes, kAlign) > s->arena.size()) return set_error(SWE_E_NOMEM, "request larger than the arena");
     copy_request(r, q.get());
+    std::lock_guard<std::mutex> g(s->qlock);
     s->pending.push_back(std::move(q));
     s->submitted += 1;
     return SWE_OK;
@@ -398,8 +446,12 @@ int swe_server_tick(swe_server *s, int32_t *n_active, int32_t *n_pending)
         s->dirty = true;
     }
     s->active = std::move(keep);
+    if (s->active.empty()) release_queue_blocks(s);
     if (n_active) *n_active = (int32_t)s->active.size();
-    if (n_pending) *n_pending = (int32_t)s->pending.size();
+    if (n_pending) {
+        std::lock_guard<std::mutex> g(s->qlock);
+        *n_pending = (int32_t)s->pending.size();
+    }
     return SWE_OK;
 }
 
@@ -418,6 +470,7 @@ int swe_server_poll(swe_server *s, swe_completion *out, int32_t max, int32_t *n)
 int swe_server_get_stats(swe_server *s, swe_server_stats *st)
 {
     if (!s || !st) return set_error(SWE_E_ARG, "NULL argument");
+    std::lock_guard<std::mutex> g(s->qlock);
     st->submitted = s->submitted;
     st->admitted = s->admitted;
     st->completed = s->completed;

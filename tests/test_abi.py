@@ -142,6 +142,42 @@ def test_ensemble_arguments_rejected_without_gpu(lib):
     lib.swe_ensemble_destroy(None)
 
 
+def test_server_arguments_rejected_without_gpu(lib):
+    import ctypes as C
+    from paper_1912_02457_amd import swe
+    h = C.c_void_p()
+    fake = C.c_void_p(1 << 20)  # never dereferenced: validation fails first
+    assert lib.swe_server_create(None, 1 << 20, None, None, 4, 8, 0, 0, C.byref(h)) == swe.SWE_E_ARG
+    assert lib.swe_server_create(fake, 1 << 20, None, None, 0, 8, 0, 0, C.byref(h)) == swe.SWE_E_ARG
+    assert lib.swe_server_create(fake, 1 << 20, None, None, 4, 0, 0, 0, C.byref(h)) == swe.SWE_E_ARG
+    assert lib.swe_server_create(C.c_void_p((1 << 20) + 8), 1 << 20, None, None, 4, 8, 0, 0,
+                                 C.byref(h)) == swe.SWE_E_ARG
+    assert lib.swe_server_submit(None, None) == swe.SWE_E_ARG
+    assert lib.swe_server_tick(None, None, None) == swe.SWE_E_ARG
+    n = C.c_int32()
+    assert lib.swe_server_poll(None, None, 0, C.byref(n)) == swe.SWE_E_ARG
+    assert lib.swe_server_get_stats(None, None) == swe.SWE_E_ARG
+    lib.swe_server_destroy(None)
+
+
+def test_request_struct_layout_matches_header():
+    import subprocess
+    import tempfile
+    from paper_1912_02457_amd import swe
+    src = ('#include <stddef.h>\n#include <stdio.h>\n#include "swe.h"\nint main(){printf("%zu %zu %zu %zu %zu %zu\\n",'
+           'sizeof(swe_request), offsetof(swe_request, horizon), offsetof(swe_request, n_wind),'
+           'offsetof(swe_request, out_hv), sizeof(swe_completion), sizeof(swe_server_stats));return 0;}\n')
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "t")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = [int(x) for x in subprocess.check_output([exe]).decode().split()]
+    R = swe.Request
+    assert out == [C.sizeof(R), R.horizon.offset, R.n_wind.offset, R.out_hv.offset,
+                   C.sizeof(swe.Completion), C.sizeof(swe.ServerStats)]
+
+
 def test_product_path_has_no_oracle_or_cpu_fallback():
     """The package never imports the oracle and has no numpy time stepping."""
     pkg = os.path.join(ROOT, "paper_1912_02457_amd")

@@ -19,6 +19,7 @@ from .configs import (  # noqa: F401
     config3,
     config4_member,
     config4_sizes,
+    config5_member,
     config5_requests,
     convergence_case,
     perimeter_len,

@@ -210,9 +210,23 @@ int get_graph(swe_domain *d, int steps, int parity, hipGraphExec_t *out)
 
 int read_ctrl(swe_domain *d, Ctrl *c)
 {
-    HIP_TRY(hipMemcpyAsync(c, d->dom.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, d->stream));
+    if (!d->pinned_ctrl) HIP_TRY(hipHostMalloc((void **)&d->pinned_ctrl, sizeof(Ctrl), hipHostMallocDefault));
+    HIP_TRY(hipMemcpyAsync(d->pinned_ctrl, d->dom.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, d->stream));
     HIP_TRY(hipStreamSynchronize(d->stream));
+    std::memcpy(c, d->pinned_ctrl, sizeof(Ctrl));
     return SWE_OK;
+}
+
+// True for memory the device cannot address directly (plain pageable host
+// memory): such destinations are filled through the pinned staging planes.
+bool is_pageable(const void *p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return true;
+    }
+    return a.type == hipMemoryTypeUnregistered;
 }
 
 }  // namespace
@@ -469,14 +483,25 @@ int swe_read_state(swe_domain *d, float *eta, float *hu, float *hv, double *t, d
     const int nx = d->p.nx, ny = d->p.ny;
     float *dst[3] = {eta, hu, hv};
     float *src[3] = {d->dom.eta, d->dom.hu, d->dom.hv};
+    const size_t plane = (size_t)nx * ny;
+    bool staged[3] = {false, false, false};
     for (int k = 0; k < 3; ++k) {
         if (!dst[k]) continue;
-        HIP_TRY(hipMemcpy2DAsync(dst[k], (size_t)nx * sizeof(float), src[k], (size_t)d->dom.pitch * sizeof(float),
+        float *to = dst[k];
+        if (is_pageable(dst[k])) {
+            if (!d->pinned_state)
+                HIP_TRY(hipHostMalloc((void **)&d->pinned_state, 3 * plane * sizeof(float), hipHostMallocDefault));
+            to = d->pinned_state + k * plane;
+            staged[k] = true;
+        }
+        HIP_TRY(hipMemcpy2DAsync(to, (size_t)nx * sizeof(float), src[k], (size_t)d->dom.pitch * sizeof(float),
                                  (size_t)nx * sizeof(float), (size_t)ny, hipMemcpyDefault, d->stream));
     }
     Ctrl c;
-    int rc = read_ctrl(d, &c);
+    int rc = read_ctrl(d, &c);  // also waits for the copies above
     if (rc) return rc;
+    for (int k = 0; k < 3; ++k)
+        if (staged[k]) std::memcpy(dst[k], d->pinned_state + k * plane, plane * sizeof(float));
     if (t) *t = c.t[d->parity];
     if (dt_next) {
         float wm = ctrl_wmax(c, d->parity);
@@ -591,6 +616,8 @@ void swe_destroy(swe_domain *d)
     for (auto g : d->graph_objs) (void)hipGraphDestroy(g);
     for (auto e : d->ev_pool) (void)hipEventDestroy(e);
     if (d->capture_stream) (void)hipStreamDestroy(d->capture_stream);
+    if (d->pinned_ctrl) (void)hipHostFree(d->pinned_ctrl);
+    if (d->pinned_state) (void)hipHostFree(d->pinned_state);
     delete d;
 }
 

@@ -58,4 +58,9 @@ struct swe_domain {
     int cus = 256;
     swe_ensemble *ensemble = nullptr;  // set while the domain belongs to an ensemble
     hipStream_t own_stream = nullptr;  // the domain's stream outside the ensemble
+    // Pinned host staging: device-to-host copies land here (a DMA that is
+    // complete once the stream is synchronised) before a plain host copy to
+    // the caller's pageable memory.
+    swe::Ctrl *pinned_ctrl = nullptr;
+    float *pinned_state = nullptr;  // 3 planes of nx*ny, allocated on first use
 };

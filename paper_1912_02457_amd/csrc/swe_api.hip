@@ -68,7 +68,11 @@ int validate(const swe_params *p)
 {
     if (!p) return fail(SWE_E_ARG, "params is NULL");
     if (p->nx < 2 || p->ny < 2) return fail(SWE_E_ARG, "nx and ny must be >= 2");
-    if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(SWE_E_ARG, "domain too large");
+    // the kernels address a plane with 32-bit byte offsets: the corner-depth
+    // plane, the largest, must stay below 4 GiB (about 1.07e9 cells)
+    if (p->nx > (1 << 29) || p->ny > (1 << 29) ||
+        (int64_t)(p->ny + 1) * (int64_t)(((int64_t)p->nx + 1 + 63) / 64 * 64) * 4 >= ((int64_t)1 << 32))
+        return fail(SWE_E_ARG, "domain too large: one plane must stay below 4 GiB");
     if (!(std::isfinite(p->dx) && p->dx > 0 && std::isfinite(p->dy) && p->dy > 0))
         return fail(SWE_E_ARG, "dx and dy must be finite and > 0");
     if (!(std::isfinite(p->g) && p->g > 0)) return fail(SWE_E_ARG, "g must be > 0");

@@ -34,6 +34,19 @@ namespace swe {
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Plane accesses by 32-bit element offset.  The byte offset is formed in 32
+// bits (every plane is below 4 GiB, checked at init), so the access uses the
+// scalar-base + 32-bit vector-offset addressing form and needs no 64-bit
+// address arithmetic per lane.
+__device__ __forceinline__ float ld(const float *__restrict__ base, uint32_t off)
+{
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + (off << 2));
+}
+__device__ __forceinline__ void st(float *__restrict__ base, uint32_t off, float v)
+{
+    *reinterpret_cast<float *>(reinterpret_cast<char *>(base) + (off << 2)) = v;
+}
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Value held by lane-1 / lane+1 through a whole-wave DPP shift (wave_shr:1
@@ -61,7 +74,8 @@ __device__ __forceinline__ float limited(float dm, float dp, float th)
 {
     float a = th * dm, b = 0.5f * (dm + dp), c = th * dp;
     float mn = fminf(a, fminf(b, c)), mx = fmaxf(a, fmaxf(b, c));
-    return mn > 0.f ? mn : (mx < 0.f ? mx : 0.f);
+    // mn if all three are positive, mx if all are negative, else 0
+    return fmaxf(mn, 0.f) + fminf(mx, 0.f);
 }
 
 __device__ __forceinline__ void time_weights(int n, const double *ts, double tau, int &k, double &s)
@@ -405,7 +419,7 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
 
     float Cx, Cy;
     if (PROJ) {
-        float ang = store ? d.north[(uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i] : 0.f;
+        float ang = store ? ld(d.north, (uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i) : 0.f;
         float cc = __cosf(ang), ss = __sinf(ang);
         float hue = cc * A.u - ss * A.v, hvn = ss * A.u + cc * A.v;
         Cx = A.f * (cc * hvn - ss * hue);
@@ -428,9 +442,9 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
         float un = (A.u + dt * Mu) * den;
         float vn = (A.v + dt * Mv) * den;
         if (store) {
-            d.eta1[oo] = en;
-            d.hu1[oo] = un;
-            d.hv1[oo] = vn;
+            st(d.eta1, oo, en);
+            st(d.hu1, oo, un);
+            st(d.hv1, oo, vn);
         }
     } else {
         float den = rcp(1.f + 0.5f * dt * S);
@@ -448,9 +462,9 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
             vn = (1.f - al) * vn + al * ex[2];
         }
         if (store) {
-            d.eta[oo] = en;
-            d.hu[oo] = un;
-            d.hv[oo] = vn;
+            st(d.eta, oo, en);
+            st(d.hu, oo, un);
+            st(d.hv, oo, vn);
         }
         // eq. cfl on the new state
         float h = en + A.Hb;
@@ -491,13 +505,13 @@ __device__ __forceinline__ RawRow load_row(const Dom &d, const float *__restrict
     if (!GHOST) {
         const uint32_t off = (uint32_t)r * (uint32_t)d.pitch + (uint32_t)il;
         const uint32_t cof = (uint32_t)(r + 1) * (uint32_t)d.cpitch + (uint32_t)il;
-        w.e = E[off];
-        w.u = U[off];
-        w.v = V[off];
-        w.f = d.f[off];
-        w.cn0 = d.Hc[cof];
-        w.cn1 = d.Hc[cof + 1];
-        w.th = PROJ ? d.north[off] : 0.f;
+        w.e = ld(E, off);
+        w.u = ld(U, off);
+        w.v = ld(V, off);
+        w.f = ld(d.f, off);
+        w.cn0 = ld(d.Hc, cof);
+        w.cn1 = ld(d.Hc, cof + 1);
+        w.th = PROJ ? ld(d.north, off) : 0.f;
     } else {
         // A lane in a ghost column only ever contributes rows inside [0, ny);
         // its rows outside (diagonal ghosts) load some in-bounds value that is
@@ -522,18 +536,18 @@ __device__ __forceinline__ RawRow load_row(const Dom &d, const float *__restrict
             w.th = PROJ ? d.nghost[(uint32_t)layer * P + (uint32_t)idx] : 0.f;
         } else {
             const uint32_t off = (uint32_t)rm.cr * (uint32_t)d.pitch + (uint32_t)cm.ci;
-            w.e = E[off];
-            w.u = U[off];
-            w.v = V[off];
-            w.f = d.f[off];
+            w.e = ld(E, off);
+            w.u = ld(U, off);
+            w.v = ld(V, off);
+            w.f = ld(d.f, off);
             // bits 31, 30, 29: flip hu, hv, f (a wall ghost negates them)
             w.flip = (cm.su < 0.f ? kSign : 0u) | (rm.sv < 0.f ? kSign >> 1 : 0u) |
                      ((cm.sf * rm.sf) < 0.f ? kSign >> 2 : 0u);
-            w.th = PROJ ? d.north[off] : 0.f;
+            w.th = PROJ ? ld(d.north, off) : 0.f;
         }
         const uint32_t cof = (uint32_t)rm.crc * (uint32_t)d.cpitch;
-        w.cn0 = d.Hc[cof + (uint32_t)cm.cc0];
-        w.cn1 = d.Hc[cof + (uint32_t)cm.cc1];
+        w.cn0 = ld(d.Hc, cof + (uint32_t)cm.cc0);
+        w.cn1 = ld(d.Hc, cof + (uint32_t)cm.cc1);
     }
     return w;
 }
@@ -549,13 +563,13 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
     float cs0, cs1;  // south corners of the row loaded next
     if (!GHOST) {
         const uint32_t cof = (uint32_t)(y0 - 2) * (uint32_t)d.cpitch + (uint32_t)il;
-        cs0 = d.Hc[cof];
-        cs1 = d.Hc[cof + 1];
+        cs0 = ld(d.Hc, cof);
+        cs1 = ld(d.Hc, cof + 1);
     } else {
         cm = col_map(d, il);
         const uint32_t cof = (uint32_t)map_corner(y0 - 2, d.ny, d.bc[2], d.bc[3]) * (uint32_t)d.cpitch;
-        cs0 = d.Hc[cof + (uint32_t)cm.cc0];
-        cs1 = d.Hc[cof + (uint32_t)cm.cc1];
+        cs0 = ld(d.Hc, cof + (uint32_t)cm.cc0);
+        cs1 = ld(d.Hc, cof + (uint32_t)cm.cc1);
     }
     const int klast = y1 + 1;
     RawRow nxt = load_row<PROJ, GHOST>(d, E, U, V, il, cm, y0 - 2, c);
@@ -603,9 +617,9 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
         float e0 = 0.f, u0 = 0.f, v0 = 0.f;
         if (STAGE == 2 && (!GHOST || c.out_lane)) {
             const uint32_t oq = (uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i;
-            e0 = d.eta[oq];
-            u0 = d.hu[oq];
-            v0 = d.hv[oq];
+            e0 = ld(d.eta, oq);
+            u0 = ld(d.hu, oq);
+            v0 = ld(d.hv, oq);
         }
         FrsPre fp;
         fp.zone = false;
@@ -615,7 +629,9 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
         float us, vs;
         y_faces(B, C, A.land, d, us, vs);
         F3 Gn = y_flux(A, B, us, vs, d);
-        finish_row<STAGE, PROJ, FRS>(A, Gs, Gn, c, e0, u0, v0, fp, d, wmax_loc, bad);
+        // a row whose output cells are all land has nothing to update
+        if (__ballot(c.out_lane && !A.land) != 0)
+            finish_row<STAGE, PROJ, FRS>(A, Gs, Gn, c, e0, u0, v0, fp, d, wmax_loc, bad);
         Gs = Gn;
     };
     for (int k = y0 + 2;;) {

@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-max-active", type=int, default=64)
+    ap.add_argument("--serve-steps-per-tick", type=int, default=24)
+    ap.add_argument("--serve-rows", type=int, default=0, help="rows per tile of the server's ensemble (0 = default)")
     ap.add_argument("--serve-time-scale", type=float, default=0.1,
                     help="factor on horizons and inter-arrival times of the request stream")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -115,7 +118,9 @@ def bench_single(a, np, torch):
     land_cells = int(np.count_nonzero(wl.land)) if wl.land is not None else 0
     wet_cells = cells - land_cells
     dom = Domain.from_workload(wl, device="cuda:0")
-    rows_per_wave, tile_order, waves = dom.tiling()
+    dom.autotune()  # measured tile height (does not advance the simulation)
+    rows_per_wave, tile_order, waves = dom.tiling(1)
+    rows2, _, waves2 = dom.tiling(2)
 
     dom.step(a.warmup)
     torch.cuda.synchronize()
@@ -184,7 +189,8 @@ def bench_single(a, np, torch):
             "nx": wl.nx, "ny": wl.ny, "dx_m": wl.dx, "cells": cells, "land_fraction": land_cells / cells,
             "boundaries": "nested (M2 tide, hourly snapshots) on all sides", "friction": "linear r=3e-3 m/s",
             "wind_stress_Nm2": 0.1, "courant": wl.courant, "dt_s": dt_next,
-            "rows_per_wave": rows_per_wave, "tile_order": tile_order, "waves_per_stage": waves,
+            "rows_per_wave": [rows_per_wave, rows2], "tile_order": tile_order, "waves_per_stage": [waves, waves2],
+            "tiling": "measured per stage kernel before the timed region (swe_autotune_tiling)",
         },
         "roofline": {
             "bound": "hbm",
@@ -295,7 +301,8 @@ def bench_serving(a, torch):
     reqs = config5_requests()[: a.serve_requests]
     arrivals = np.array([r["arrival"] for r in reqs]) * sc
     horizons = [r["horizon"] * sc for r in reqs]
-    srv = Server(48 << 30, max_active=64, steps_per_tick=24, device="cuda:0")
+    srv = Server(48 << 30, max_active=a.serve_max_active, steps_per_tick=a.serve_steps_per_tick,
+                 rows_per_wave=a.serve_rows, device="cuda:0")
     done_at = {}
     submitted = threading.Event()
     errors = []
@@ -324,15 +331,23 @@ def bench_serving(a, torch):
     t0 = time.perf_counter()
     th = threading.Thread(target=feeder, daemon=True)
     th.start()
+    busy_s = 0.0  # wall time of ticks that had requests resident
+    active_time = 0.0  # integral of the active count over time
+    last = t0
     while True:
         act, pend = srv.tick()
         now = time.perf_counter()
+        if act:
+            busy_s += now - last
+            active_time += act * (now - last)
+        last = now
         for c in srv.poll():
             done_at[c["id"]] = (now, c["status"], c["steps"])
         if submitted.is_set() and act == 0 and pend == 0:
             break
         if act == 0 and pend == 0:
             time.sleep(2e-4)
+            last = time.perf_counter()
     th.join()
     if errors:
         raise errors[0]
@@ -354,8 +369,11 @@ def bench_serving(a, torch):
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "max": float(lat.max()), "mean": float(lat.mean())},
         "offered_cell_steps_per_s": float(offered / (arrivals[-1] - arrivals[0] + 1e-9)),
-        "span_s": span, "ticks": st["ticks"], "steps_per_tick": 24, "max_active": 64,
+        "span_s": span, "busy_s": busy_s, "mean_active": active_time / max(busy_s, 1e-9),
+        "ticks": st["ticks"], "steps_per_tick": a.serve_steps_per_tick, "max_active": a.serve_max_active,
+        "rows_per_wave": a.serve_rows,
         "arena_peak_GiB": st["arena_peak"] / 2**30,
+        "host_s": {k[5:-2]: round(st[k], 3) for k in st if k.startswith("host_")},
     }
 
 

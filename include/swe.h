@@ -153,6 +153,15 @@ int swe_diagnostics(swe_domain *d, double *mass, double *energy);
  * Synchronises. */
 int swe_status(swe_domain *d);
 
+/* Measures both stage kernels of this domain for rows per tile in {2..64}
+ * (a few launches each) and keeps the fastest per stage.  The state and the
+ * control block are saved to host memory first and restored afterwards, so
+ * the simulation does not advance.  *rows_per_wave gets stage 1's choice
+ * (may be NULL; swe_get_tiling reports each stage).  Synchronises.  Errors:
+ * SWE_E_STATE inside an ensemble or without boundary data for nested sides,
+ * SWE_E_HIP. */
+int swe_autotune_tiling(swe_domain *d, int32_t *rows_per_wave);
+
 /* Work decomposition of the stage kernels: each wavefront updates a strip of
  * 60 columns over rows_per_wave rows (0 = the built-in choice per stage
  * kernel, which fills the wave slots its register use allows in whole
@@ -160,9 +169,9 @@ int swe_status(swe_domain *d);
  * (bit 0: row-block-major instead of strip-major, bit 1: no grouping of
  * neighbouring tiles per XCD; -1 = default).  Used by the autotuner; results
  * do not depend on it (bitwise).  swe_get_tiling reports the values and the
- * wavefronts per launch of the first stage kernel. */
+ * wavefronts per launch of stage kernel `stage` (1 or 2). */
 int swe_set_tiling(swe_domain *d, int32_t rows_per_wave, int32_t order);
-int swe_get_tiling(swe_domain *d, int32_t *rows_per_wave, int32_t *order, int32_t *waves);
+int swe_get_tiling(swe_domain *d, int32_t stage, int32_t *rows_per_wave, int32_t *order, int32_t *waves);
 
 /* Average device time per launch of each stage kernel (milliseconds) over
  * the launches issued since the last call with reset != 0, measured with HIP
@@ -271,6 +280,10 @@ typedef struct swe_server_stats {
     int64_t cell_steps;             /* sum over requests of cells x steps taken so far */
     size_t arena_bytes, arena_used, arena_peak;
     int32_t active, pending;
+    /* host wall time spent in the parts of swe_server_tick, seconds:
+     * rebuilding the work queue, launching the steps, admitting (uploads),
+     * waiting for the device, retiring (result copies, frees) */
+    double host_rebuild_s, host_launch_s, host_admit_s, host_wait_s, host_retire_s;
 } swe_server_stats;
 
 /* dev_arena: caller-owned device memory (256-byte aligned) from which every

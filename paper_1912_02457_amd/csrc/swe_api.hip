@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <map>
 #include <string>
 #include <utility>
@@ -97,9 +98,13 @@ int validate(const swe_params *p)
 
 bool all_finite(const float *a, size_t n)
 {
-    for (size_t k = 0; k < n; ++k)
-        if (!std::isfinite(a[k])) return false;
-    return true;
+    uint32_t bad = 0;  // branch-free so that the loop vectorises
+    for (size_t k = 0; k < n; ++k) {
+        uint32_t b;
+        std::memcpy(&b, a + k, sizeof b);
+        bad |= (uint32_t)((b & 0x7f800000u) == 0x7f800000u);
+    }
+    return bad == 0;
 }
 
 bool any_nested(const swe_params &p)
@@ -115,12 +120,75 @@ int swe::set_error(int code, const std::string &msg) { return fail(code, msg); }
 
 namespace {
 
-int upload_pitched(swe_domain *d, size_t off, const float *src, int w, int h, int pitch, hipStream_t s)
-{
-    HIP_TRY(hipMemcpy2DAsync(d->ws + off, (size_t)pitch * sizeof(float), src, (size_t)w * sizeof(float),
-                             (size_t)w * sizeof(float), (size_t)h, hipMemcpyHostToDevice, s));
-    return SWE_OK;
-}
+// Host-to-device uploads go through one process-wide pinned staging buffer
+// (at most 64 MiB, larger arrays go in row chunks): a copy from pageable
+// memory straight into a pitched device plane would be split by the runtime
+// into row-sized transfers.  The buffer is held for the whole upload
+// sequence of one call.
+constexpr size_t kStageCap = (size_t)64 << 20;
+std::mutex g_stage_mu;
+char *g_stage = nullptr;
+size_t g_stage_bytes = 0;
+
+class Uploader {
+public:
+    Uploader(hipStream_t s, size_t hint) : lk_(g_stage_mu), s_(s) { hint_ = std::min(hint, kStageCap); }
+    ~Uploader()
+    {
+        if (pending_) (void)hipStreamSynchronize(s_);
+    }
+    // w x h floats (rows of w) into device rows of dpitch floats at dst
+    hipError_t plane(void *dst, int dpitch, const float *src, int w, int h)
+    {
+        const size_t rowb = (size_t)w * sizeof(float);
+        hipError_t e;
+        if ((e = ensure(std::max(rowb, hint_))) != hipSuccess) return e;
+        for (int r0 = 0; r0 < h;) {
+            size_t room = g_stage_bytes - used_;
+            if (room < rowb) {
+                if ((e = flush()) != hipSuccess) return e;
+                room = g_stage_bytes;
+            }
+            const int rows = (int)std::min<size_t>((size_t)(h - r0), room / rowb);
+            char *stg = g_stage + used_;
+            std::memcpy(stg, src + (size_t)r0 * w, (size_t)rows * rowb);
+            e = hipMemcpy2DAsync((char *)dst + (size_t)r0 * dpitch * sizeof(float), (size_t)dpitch * sizeof(float),
+                                 stg, rowb, rowb, (size_t)rows, hipMemcpyHostToDevice, s_);
+            if (e != hipSuccess) return e;
+            pending_ = true;
+            used_ += ((size_t)rows * rowb + 255) / 256 * 256;
+            r0 += rows;
+        }
+        return hipSuccess;
+    }
+    hipError_t flush()
+    {
+        hipError_t e = pending_ ? hipStreamSynchronize(s_) : hipSuccess;
+        pending_ = false;
+        used_ = 0;
+        return e;
+    }
+
+private:
+    hipError_t ensure(size_t need)
+    {
+        if (g_stage_bytes >= need) return hipSuccess;
+        if (pending_) {
+            hipError_t e = flush();
+            if (e != hipSuccess) return e;
+        }
+        if (g_stage) (void)hipHostFree(g_stage);
+        g_stage = nullptr;
+        g_stage_bytes = 0;
+        hipError_t e = hipHostMalloc((void **)&g_stage, need, hipHostMallocDefault);
+        if (e == hipSuccess) g_stage_bytes = need;
+        return e;
+    }
+    std::unique_lock<std::mutex> lk_;
+    hipStream_t s_;
+    size_t hint_ = 0, used_ = 0;
+    bool pending_ = false;
+};
 
 // f of the two ghost layers of nested sides: the mirrored interior cell
 // (layer 0 <- the outermost interior cell, layer 1 <- the next one), with the
@@ -210,6 +278,15 @@ int get_graph(swe_domain *d, int steps, int parity, hipGraphExec_t *out)
     d->graphs[key] = ex;
     *out = ex;
     return SWE_OK;
+}
+
+// Captured step graphs embed the tiling: dropped when it changes.
+void drop_graphs(swe_domain *d)
+{
+    for (auto &kv : d->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto g : d->graph_objs) (void)hipGraphDestroy(g);
+    d->graphs.clear();
+    d->graph_objs.clear();
 }
 
 int read_ctrl(swe_domain *d, Ctrl *c)
@@ -339,20 +416,20 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
     build_ghost_table(*p, theta, ng);
     for (int k = 0; k < kMaxFrs; ++k) alpha[k] = (float)(1.0 - std::tanh((double)k / p->frs_d0));
     static const Ctrl c0{};
-    if ((r = upload_pitched(d, L.eta, eta, nx, ny, D.pitch, s)) ||
-        (r = upload_pitched(d, L.hu, hu, nx, ny, D.pitch, s)) ||
-        (r = upload_pitched(d, L.hv, hv, nx, ny, D.pitch, s)) ||
-        (r = upload_pitched(d, L.Hc, Hc, nx + 1, ny + 1, D.cpitch, s)) ||
-        (r = upload_pitched(d, L.f, fl.data(), nx, ny, D.pitch, s))) {
-        delete d;
-        return r;
-    }
-    if (p->north_projection) {
-        std::vector<float> th0(nc, 0.f);
-        if ((r = upload_pitched(d, L.north, theta ? theta : th0.data(), nx, ny, D.pitch, s))) { delete d; return r; }
-        (void)hipStreamSynchronize(s);
-    }
     hipError_t e;
+    {
+        Uploader up(s, (5 + (p->north_projection ? 1 : 0)) * (nk + 64 * (size_t)(ny + 1)) * sizeof(float));
+        std::vector<float> th0;
+        if (p->north_projection && !theta) th0.assign(nc, 0.f);
+        if ((e = up.plane(w + L.eta, D.pitch, eta, nx, ny)) || (e = up.plane(w + L.hu, D.pitch, hu, nx, ny)) ||
+            (e = up.plane(w + L.hv, D.pitch, hv, nx, ny)) || (e = up.plane(w + L.Hc, D.cpitch, Hc, nx + 1, ny + 1)) ||
+            (e = up.plane(w + L.f, D.pitch, fl.data(), nx, ny)) ||
+            (p->north_projection && (e = up.plane(w + L.north, D.pitch, theta ? theta : th0.data(), nx, ny))) ||
+            (e = up.flush())) {
+            delete d;
+            return hip_fail(e, "upload");
+        }
+    }
     if ((e = hipMemcpyAsync(w + L.fghost, fg.data(), fg.size() * sizeof(float), hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(w + L.nghost, ng.data(), ng.size() * sizeof(float), hipMemcpyHostToDevice, s)) ||
         (e = hipMemcpyAsync(w + L.alpha, alpha.data(), alpha.size() * sizeof(float), hipMemcpyHostToDevice, s)) ||
@@ -405,10 +482,7 @@ int swe_set_forcing(swe_domain *d, int32_t kind, int32_t n_times, const double *
         return fail(SWE_E_ARG, "unknown forcing kind");
     }
     // kernel arguments changed: captured graphs are stale
-    for (auto &kv : d->graphs) (void)hipGraphExecDestroy(kv.second);
-    for (auto g : d->graph_objs) (void)hipGraphDestroy(g);
-    d->graphs.clear();
-    d->graph_objs.clear();
+    drop_graphs(d);
     return SWE_OK;
 }
 
@@ -524,9 +598,14 @@ int swe_set_state(swe_domain *d, const float *eta, const float *hu, const float 
     if (!std::isfinite(t) || !all_finite(eta, nc) || !all_finite(hu, nc) || !all_finite(hv, nc))
         return fail(SWE_E_ARG, "non-finite state");
     int rc;
-    if ((rc = upload_pitched(d, d->L.eta, eta, nx, ny, d->dom.pitch, d->stream)) ||
-        (rc = upload_pitched(d, d->L.hu, hu, nx, ny, d->dom.pitch, d->stream)) ||
-        (rc = upload_pitched(d, d->L.hv, hv, nx, ny, d->dom.pitch, d->stream)) || (rc = copy_state_to_star(d)) ||
+    {
+        Uploader up(d->stream, 3 * nc * sizeof(float));
+        hipError_t e;
+        if ((e = up.plane(d->dom.eta, d->dom.pitch, eta, nx, ny)) || (e = up.plane(d->dom.hu, d->dom.pitch, hu, nx, ny)) ||
+            (e = up.plane(d->dom.hv, d->dom.pitch, hv, nx, ny)) || (e = up.flush()))
+            return hip_fail(e, "upload");
+    }
+    if ((rc = copy_state_to_star(d)) ||
         (rc = reset_time_and_cfl(d, t)))
         return rc;
     HIP_TRY(hipStreamSynchronize(d->stream));
@@ -565,19 +644,84 @@ int swe_set_tiling(swe_domain *d, int32_t rows_per_wave, int32_t order)
         d->T[st] = make_tiling(d->p.nx, d->p.ny, by);
         if (order >= 0) d->T[st].order = order;
     }
-    for (auto &kv : d->graphs) (void)hipGraphExecDestroy(kv.second);
-    for (auto g : d->graph_objs) (void)hipGraphDestroy(g);
-    d->graphs.clear();
-    d->graph_objs.clear();
+    drop_graphs(d);
     return SWE_OK;
 }
 
-int swe_get_tiling(swe_domain *d, int32_t *rows_per_wave, int32_t *order, int32_t *waves)
+// Time one stage kernel over candidate tile heights (one warm-up and four
+// event-timed launches each); returns the fastest.
+int sweep_stage(swe_domain *d, int stage, int *best_by)
+{
+    static const int cand[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 32, 48, 64};
+    const bool proj = d->p.north_projection != 0;
+    hipEvent_t ev[8];
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    int best = d->T[stage - 1].by;
+    float best_ms = INFINITY;
+    hipError_t he = hipSuccess;
+    for (int by : cand) {
+        if (by > d->p.ny && by != cand[0]) break;
+        Tiling T = make_tiling(d->p.nx, d->p.ny, by);
+        if ((he = launch_stage(stage, proj, d->dom, T, d->parity, 0.0, d->stream, nullptr, nullptr)) != hipSuccess)
+            break;
+        for (int k = 0; k < 4 && he == hipSuccess; ++k)
+            he = launch_stage(stage, proj, d->dom, T, d->parity, 0.0, d->stream, ev[2 * k], ev[2 * k + 1]);
+        if (he != hipSuccess || (he = hipStreamSynchronize(d->stream)) != hipSuccess) break;
+        float tot = 0.f;
+        for (int k = 0; k < 4 && he == hipSuccess; ++k) {
+            float ms = 0.f;
+            he = hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]);
+            tot += ms;
+        }
+        if (he != hipSuccess) break;
+        if (tot < best_ms * 0.99f) { best_ms = tot; best = by; }
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (he != hipSuccess) return hip_fail(he, "tiling sweep");
+    *best_by = best;
+    return SWE_OK;
+}
+
+int swe_autotune_tiling(swe_domain *d, int32_t *rows_per_wave)
+{
+    int rc = check_ready(d);
+    if (rc) return rc;
+    // Stage 1 writes only Q*, which every step overwrites; stage 2 writes
+    // Q^{n+1} over Q^n.  Q^n and the control block (time, step count, CFL
+    // slots) are saved first and put back afterwards, so the sweep leaves the
+    // simulation where it was.
+    Ctrl saved;
+    if ((rc = read_ctrl(d, &saved))) return rc;
+    const int nx = d->p.nx, ny = d->p.ny;
+    const size_t plane = (size_t)nx * ny, row = (size_t)nx * sizeof(float), dp = (size_t)d->dom.pitch * sizeof(float);
+    if (!d->pinned_state) HIP_TRY(hipHostMalloc((void **)&d->pinned_state, 3 * plane * sizeof(float), hipHostMallocDefault));
+    float *q[3] = {d->dom.eta, d->dom.hu, d->dom.hv};
+    for (int k = 0; k < 3; ++k)
+        HIP_TRY(hipMemcpy2DAsync(d->pinned_state + k * plane, row, q[k], dp, row, ny, hipMemcpyDeviceToHost, d->stream));
+    int by1 = 0, by2 = 0;
+    if ((rc = sweep_stage(d, 1, &by1))) return rc;
+    HIP_TRY(launch_stage(1, d->p.north_projection != 0, d->dom, make_tiling(nx, ny, by1), d->parity, 0.0, d->stream,
+                         nullptr, nullptr));
+    if ((rc = sweep_stage(d, 2, &by2))) return rc;
+    for (int k = 0; k < 3; ++k)
+        HIP_TRY(hipMemcpy2DAsync(q[k], dp, d->pinned_state + k * plane, row, row, ny, hipMemcpyHostToDevice, d->stream));
+    HIP_TRY(hipMemcpyAsync(d->dom.ctrl, &saved, sizeof(Ctrl), hipMemcpyHostToDevice, d->stream));
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    d->T[0] = make_tiling(nx, ny, by1);
+    d->T[1] = make_tiling(nx, ny, by2);
+    drop_graphs(d);
+    if (rows_per_wave) *rows_per_wave = by1;
+    return SWE_OK;
+}
+
+int swe_get_tiling(swe_domain *d, int32_t stage, int32_t *rows_per_wave, int32_t *order, int32_t *waves)
 {
     if (!d) return fail(SWE_E_ARG, "domain is NULL");
-    if (rows_per_wave) *rows_per_wave = d->T[0].by;
-    if (order) *order = d->T[0].order;
-    if (waves) *waves = d->T[0].ntiles;
+    if (stage != 1 && stage != 2) return fail(SWE_E_ARG, "stage must be 1 or 2");
+    const Tiling &T = d->T[stage - 1];
+    if (rows_per_wave) *rows_per_wave = T.by;
+    if (order) *order = T.order;
+    if (waves) *waves = T.ntiles;
     return SWE_OK;
 }
 

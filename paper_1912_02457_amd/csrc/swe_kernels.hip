@@ -16,10 +16,10 @@
 //     (g/2dx)(h^E + h^W)(H_E - H_W); the two parts cancel exactly, so M is
 //     unchanged, but the float32 flux difference no longer carries the
 //     cancellation of g H^2/2 ~ 4e7 at 3000 m (section "Accuracy, precision
-//     and GPUs" motivates eta for the same reason).  Where both faces of a
-//     cell are below the datum the source becomes (g/dx) eta (H_E - H_W)
-//     (eta^E + eta^W = 2 eta); above the datum (dry land, H < 0) nothing is
-//     subtracted and a dry cell stays exactly at rest;
+//     and GPUs" motivates eta for the same reason).  The source then reads
+//     (g/2dx)[(eta^E + eta^W)(H_E - H_W) + min(H_E,0)^2 - min(H_W,0)^2]:
+//     below the datum only the eta part remains, above it (dry land, H < 0)
+//     nothing is subtracted and a dry cell stays exactly at rest;
 //   * the north-vector projection of the Coriolis term (section "Coriolis
 //     force") returns f (hv, -hu) for every angle; the default variant uses
 //     that identity, PROJ = true evaluates the projection literally.
@@ -241,13 +241,14 @@ __device__ __forceinline__ F3 face_flux(float eL, float pL, float qL, float eR, 
 
 // bathymetry source times dx (x) or dy (y): (g/2)(h^E + h^W)(H_E - H_W)
 // minus g (R_E^2 - R_W^2)/2, R = max(H, 0), matching the pressure flux of
-// cu_flux.  With both faces below the datum it is g eta (H_E - H_W).
-__device__ __forceinline__ float bathy_source(float eta, float eE, float eW, float HE, float HW, const Dom &d)
+// cu_flux.  With h = eta + H and H^2 - max(H,0)^2 = min(H,0)^2 this is
+//   g/2 [(eta^E + eta^W)(H_E - H_W) + min(H_E,0)^2 - min(H_W,0)^2],
+// one formula for wet and dry faces with no cancellation of large terms.
+__device__ __forceinline__ float bathy_source(float eE, float eW, float HE, float HW, const Dom &d)
 {
-    float deep = d.g * eta * (HE - HW);
-    float RE = fmaxf(HE, 0.f), RW = fmaxf(HW, 0.f);
-    float gen = 0.5f * d.g * (((eE + HE) + (eW + HW)) * (HE - HW) - (RE * RE - RW * RW));
-    return (HE >= 0.f && HW >= 0.f) ? deep : gen;
+    float mE = fminf(HE, 0.f), mW = fminf(HW, 0.f);
+    float dry = fmaf(mE, mE, -(mW * mW));
+    return d.g * fmaf(0.5f * (eE + eW), HE - HW, 0.5f * dry);
 }
 
 // bed shear stress coefficient S >= 0, the source being -S (hu, hv), from the
@@ -429,10 +430,10 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
         Cy = -A.f * A.u;
     }
     float Me = -(Fe.e - Fwe) * d.rdx - (Gn.e - Gs.e) * d.rdy;
-    float Mu = -(Fe.p - Fwp) * d.rdx - (Gn.q - Gs.q) * d.rdy + bathy_source(A.e, eE, eW, A.He, A.Hw, d) * d.rdx +
+    float Mu = -(Fe.p - Fwp) * d.rdx - (Gn.q - Gs.q) * d.rdy + bathy_source(eE, eW, A.He, A.Hw, d) * d.rdx +
                Cx + c.wx;
     float Mv = -(Fe.q - Fwq) * d.rdx - (Gn.p - Gs.p) * d.rdy +
-               bathy_source(A.e, A.eN, A.eS, A.Hn, A.Hs, d) * d.rdy + Cy + c.wy;
+               bathy_source(A.eN, A.eS, A.Hn, A.Hs, d) * d.rdy + Cy + c.wy;
     const uint32_t oo = (uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i;
     const float dt = c.dt;
     float S = friction_coeff(d, A.ri, A.u, A.v);
@@ -576,7 +577,10 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
 
     auto load = [&](Row &C, int k) {
         RawRow cur = nxt;
-        if (k < klast) nxt = load_row<PROJ, GHOST>(d, E, U, V, il, cm, k + 1, c);
+        // unconditional (the last row reloads itself), so that the memory
+        // counter is the same on every path and a wait for this row's own
+        // loads never has to drain the prefetch of the next one
+        nxt = load_row<PROJ, GHOST>(d, E, U, V, il, cm, min(k + 1, klast), c);
         if (GHOST) {
             if (cur.flip & 1u) {
                 const double t = c.bs;

@@ -3,6 +3,7 @@
 // ensemble launch; this file holds the admission queue, the arena
 // allocator, the tick sequence and the completion records.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstddef>
 #include <cstring>
@@ -127,6 +128,7 @@ struct swe_server {
     bool dirty = false;  // the active set changed since the ensemble was built
     CtrlHead *heads = nullptr;  // pinned, one per active slot
     int64_t submitted = 0, admitted = 0, completed = 0, ticks = 0, cell_steps = 0;
+    double t_rebuild = 0, t_launch = 0, t_admit = 0, t_wait = 0, t_retire = 0;
 };
 
 namespace {
@@ -399,18 +401,29 @@ int swe_server_submit(swe_server *s, const swe_request *r)
 int swe_server_tick(swe_server *s, int32_t *n_active, int32_t *n_pending)
 {
     if (!s) return set_error(SWE_E_ARG, "server is NULL");
+    using clk = std::chrono::steady_clock;
+    auto secs = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); };
     int rc;
+    auto t0 = clk::now();
     if (s->dirty && (rc = rebuild(s))) return rc;
+    auto t1 = clk::now();
     // 1. the active set advances (asynchronously) ...
     if (s->ens && (rc = swe_ensemble_step(s->ens, s->steps_per_tick))) return rc;
+    auto t2 = clk::now();
     // 2. ... while waiting requests are uploaded on the other stream
     const size_t n_before = s->active.size();
     if ((rc = admit(s))) return rc;
+    auto t3 = clk::now();
     // 3. read back the control heads of the members that took part
     for (size_t k = 0; k < n_before; ++k)
         SHIP(hipMemcpyAsync(&s->heads[k], s->active[k].dom->dom.ctrl, sizeof(CtrlHead), hipMemcpyDeviceToHost,
                             s->stream));
     SHIP(hipStreamSynchronize(s->stream));
+    auto t4 = clk::now();
+    s->t_rebuild += secs(t0, t1);
+    s->t_launch += secs(t1, t2);
+    s->t_admit += secs(t2, t3);
+    s->t_wait += secs(t3, t4);
     s->ticks += 1;
     // 4. retire finished (or failed) requests; newly admitted ones join at
     //    the next tick (a zero horizon completes at once)
@@ -447,6 +460,7 @@ int swe_server_tick(swe_server *s, int32_t *n_active, int32_t *n_pending)
     }
     s->active = std::move(keep);
     if (s->active.empty()) release_queue_blocks(s);
+    s->t_retire += secs(t4, clk::now());
     if (n_active) *n_active = (int32_t)s->active.size();
     if (n_pending) {
         std::lock_guard<std::mutex> g(s->qlock);
@@ -481,6 +495,11 @@ int swe_server_get_stats(swe_server *s, swe_server_stats *st)
     st->arena_peak = s->arena.peak();
     st->active = (int32_t)s->active.size();
     st->pending = (int32_t)s->pending.size();
+    st->host_rebuild_s = s->t_rebuild;
+    st->host_launch_s = s->t_launch;
+    st->host_admit_s = s->t_admit;
+    st->host_wait_s = s->t_wait;
+    st->host_retire_s = s->t_retire;
     return SWE_OK;
 }
 

@@ -61,7 +61,8 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
                 ("ticks", C.c_int64), ("cell_steps", C.c_int64), ("arena_bytes", C.c_size_t),
                 ("arena_used", C.c_size_t), ("arena_peak", C.c_size_t), ("active", C.c_int32),
-                ("pending", C.c_int32)]
+                ("pending", C.c_int32), ("host_rebuild_s", C.c_double), ("host_launch_s", C.c_double),
+                ("host_admit_s", C.c_double), ("host_wait_s", C.c_double), ("host_retire_s", C.c_double)]
 
 
 # exported symbols of include/swe.h and their ctypes signatures
@@ -79,7 +80,9 @@ SIGNATURES = {
     "swe_diagnostics": (C.c_int, [_VP, _D, _D]),
     "swe_status": (C.c_int, [_VP]),
     "swe_set_tiling": (C.c_int, [_VP, C.c_int32, C.c_int32]),
-    "swe_get_tiling": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "swe_get_tiling": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32)]),
+    "swe_autotune_tiling": (C.c_int, [_VP, C.POINTER(C.c_int32)]),
     "swe_enable_timing": (C.c_int, [_VP, C.c_int32]),
     "swe_stage_times": (C.c_int, [_VP, _D, _D, C.POINTER(C.c_int64), C.c_int32]),
     "swe_destroy": (None, [_VP]),
@@ -270,10 +273,17 @@ class Domain:
     def set_tiling(self, rows_per_wave: int = 0, order: int = -1):
         _check(load_library().swe_set_tiling(self._h, int(rows_per_wave), int(order)))
 
-    def tiling(self):
-        """(rows per wave, tile order, wavefronts per stage launch)"""
+    def autotune(self) -> int:
+        """Time stage 1 over candidate tile heights (the simulation does not
+        advance) and keep the fastest; returns the rows per tile chosen."""
+        r = C.c_int32()
+        _check(load_library().swe_autotune_tiling(self._h, C.byref(r)))
+        return r.value
+
+    def tiling(self, stage: int = 1):
+        """(rows per wave, tile order, wavefronts per launch) of a stage kernel"""
         by, o, w = C.c_int32(), C.c_int32(), C.c_int32()
-        _check(load_library().swe_get_tiling(self._h, C.byref(by), C.byref(o), C.byref(w)))
+        _check(load_library().swe_get_tiling(self._h, int(stage), C.byref(by), C.byref(o), C.byref(w)))
         return by.value, o.value, w.value
 
     def enable_timing(self, on: bool = True):

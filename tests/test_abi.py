@@ -122,6 +122,7 @@ def test_null_handles_rejected(lib):
     from paper_1912_02457_amd import swe
     assert lib.swe_step(None, 1) == swe.SWE_E_ARG
     assert lib.swe_status(None) == swe.SWE_E_ARG
+    assert lib.swe_autotune_tiling(None, None) == swe.SWE_E_ARG
     lib.swe_destroy(None)
 
 

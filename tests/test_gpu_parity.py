@@ -253,6 +253,30 @@ def test_lake_at_rest_gpu():
     assert np.abs(u).max() == 0.0 and np.abs(v).max() == 0.0
 
 
+@pytest.mark.parametrize("which", ["walls_land", "nested_all"])
+def test_autotune_leaves_the_simulation_alone(which):
+    """The tiling sweep runs stage 1 repeatedly but restores the control
+    block: the state, time and next dt are unchanged, and the following
+    steps equal those of an untuned twin bitwise."""
+    name, nx, ny, kw = next(c for c in CASES if c[0] == which)
+    wl = random_small(nx, ny, seed=77, **kw)
+    a, b = _dom(wl), _dom(wl)
+    a.step(3)
+    b.step(3)
+    before = a.read_state()
+    by = a.autotune()
+    assert by >= 2 and a.tiling()[0] == by
+    after = a.read_state()
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    a.step(37)
+    b.step(37)
+    for x, y in zip(a.read_state(), b.read_state()):
+        assert np.array_equal(x, y)
+    a.close()
+    b.close()
+
+
 def test_tiling_does_not_change_results():
     """Rows per wave only changes the work decomposition: results are bitwise
     identical for tile heights that split the domain differently (interior

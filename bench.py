@@ -38,6 +38,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 #   land cell, either stage: read its Q (12) + Hc (4) + f (4) for the neighbours,
 #   nothing written (land is frozen)                                            = 20
 BYTES = {1: (32, 20), 2: (44, 20)}
+# The stage kernels are bound by the float32 vector ALU (VALU busy ~80 % in the
+# counter runs), so the roofline is the VALU issue rate: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz = 39.3e12 lane-instruction slots/s (no packed FP32 in
+# this build; a quarter-rate transcendental -- rcp, sqrt, exp, log -- takes 4
+# slots).  Per-cell work of each stage kernel = the VALU slots of one row step
+# of its interior tile loop, one lane per cell (gfx950 assembly of
+# swe_kernels.hip): no halo lane, halo row, boundary or tail overhead counted.
+VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
+VALU_SLOTS_PER_CELL = {1: 364 + 3 * 12, 2: 415 + 3 * 14}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_kernels_norkyst_2600x900.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1912_02457_amd", "csrc", "swe_kernels.hip")
 
@@ -167,7 +176,9 @@ def bench_single(a, np, torch):
     dominant = 2 if ms2 >= ms1 else 1
     ms_dom = ms2 if dominant == 2 else ms1
     bytes_dom = b2 if dominant == 2 else b1
-    achieved = bytes_dom / (ms_dom * 1e-3) / 1e9
+    gbs = bytes_dom / (ms_dom * 1e-3) / 1e9
+    slots_dom = VALU_SLOTS_PER_CELL[dominant] * cells
+    achieved = slots_dom / (ms_dom * 1e-3) / 1e12
     traffic = measured_traffic(f"stage{dominant}")
 
     value = cells * a.steps / el
@@ -193,14 +204,18 @@ def bench_single(a, np, torch):
             "tiling": "measured per stage kernel before the timed region (swe_autotune_tiling)",
         },
         "roofline": {
-            "bound": "hbm",
+            "bound": "alu",
             "kernel": f"stage_kernel<{dominant}>",
             "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "peak": VALU_PEAK_TSLOTS,
+            "unit": "T VALU lane-slots/s",
+            "frac": achieved / VALU_PEAK_TSLOTS,
             "traffic": traffic,
-            "algorithmic_bytes_per_launch": bytes_dom,
+            "valu_slots_per_cell": VALU_SLOTS_PER_CELL[dominant],
+            "valu_slots_per_launch": slots_dom,
+            "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                    "algorithmic_bytes_per_launch": bytes_dom,
+                    "traffic_frac": None if traffic is None else traffic / (ms_dom * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "avg_launch_ms": ms_dom,
             "stage1_ms": ms1, "stage2_ms": ms2, "timed_launches": nl,
             "timing": "HIP start/stop events around every stage launch over K steps",
@@ -333,14 +348,20 @@ def bench_serving(a, torch):
     th.start()
     busy_s = 0.0  # wall time of ticks that had requests resident
     active_time = 0.0  # integral of the active count over time
+    sat_s, sat_cells = 0.0, 0  # ticks that ran with requests still waiting
     last = t0
+    last_cells = 0
     while True:
         act, pend = srv.tick()
         now = time.perf_counter()
+        cells_now = srv.stats()["cell_steps"]
         if act:
             busy_s += now - last
             active_time += act * (now - last)
-        last = now
+        if pend:
+            sat_s += now - last
+            sat_cells += cells_now - last_cells
+        last, last_cells = now, cells_now
         for c in srv.poll():
             done_at[c["id"]] = (now, c["status"], c["steps"])
         if submitted.is_set() and act == 0 and pend == 0:
@@ -369,6 +390,8 @@ def bench_serving(a, torch):
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "max": float(lat.max()), "mean": float(lat.mean())},
         "offered_cell_steps_per_s": float(offered / (arrivals[-1] - arrivals[0] + 1e-9)),
+        "saturated_value": sat_cells / sat_s if sat_s > 0 else None,
+        "saturated_s": sat_s,
         "span_s": span, "busy_s": busy_s, "mean_active": active_time / max(busy_s, 1e-9),
         "ticks": st["ticks"], "steps_per_tick": a.serve_steps_per_tick, "max_active": a.serve_max_active,
         "rows_per_wave": a.serve_rows,

@@ -72,7 +72,7 @@ def run_gpu(name, out):
     e, u, v, t, _ = d.read_state()
     el = time.time() - t0
     d.close()
-    np.savez(os.path.join(out, f"{name}_gpu_own.npz"), eta=e, hu=u, hv=v, t=t, steps=k)
+    np.savez_compressed(os.path.join(out, f"{name}_gpu_own.npz"), eta=e, hu=u, hv=v, t=t, steps=k)
     info = {"config": name, "gpu_steps": k, "t": t, "seconds": el}
     ref = os.path.join(out, f"{name}_oracle.npz")
     if os.path.exists(ref):
@@ -81,7 +81,7 @@ def run_gpu(name, out):
         d.step_dt(dts)
         e, u, v, t, _ = d.read_state()
         d.close()
-        np.savez(os.path.join(out, f"{name}_gpu_replay.npz"), eta=e, hu=u, hv=v, t=t)
+        np.savez_compressed(os.path.join(out, f"{name}_gpu_replay.npz"), eta=e, hu=u, hv=v, t=t)
         info["replay_steps"] = len(dts)
     print(json.dumps(info), flush=True)
 

@@ -100,10 +100,11 @@ def cpu_baseline(wl, target_s):
     }
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of ``kernel`` from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE runs (scaled by the copy-kernel calibration), or
-    None when the kernel source changed since they were taken."""
+def measured_traffic(kernel: str, rows: int):
+    """HBM bytes per launch of ``kernel`` at ``rows`` rows per tile from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by the
+    copy-kernel calibration), or None when the kernel source changed since
+    they were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -114,7 +115,7 @@ def measured_traffic(kernel: str):
     src = hashlib.sha1(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     if vals.get("kernel_source_sha1") != src:
         return None
-    key = f"{kernel}_hbm_bytes_per_launch"
+    key = f"{kernel}_rows{rows}_hbm_bytes_per_launch"
     return float(vals[key]) if key in vals else None
 
 
@@ -179,7 +180,7 @@ def bench_single(a, np, torch):
     gbs = bytes_dom / (ms_dom * 1e-3) / 1e9
     slots_dom = VALU_SLOTS_PER_CELL[dominant] * cells
     achieved = slots_dom / (ms_dom * 1e-3) / 1e12
-    traffic = measured_traffic(f"stage{dominant}")
+    traffic = measured_traffic(f"stage{dominant}", rows_per_wave if dominant == 1 else rows2)
 
     value = cells * a.steps / el
     out = {

@@ -17,7 +17,8 @@ import pytest
 from oracle import oracle as O
 from tests._pinlib import G, dam_break_depth, hbar, make_wl, rel_err
 from workloads import (BC_NESTED, BC_PERIODIC, BC_WALL, FRIC_LINEAR, FRIC_MANNING,
-                       FRIC_QUADRATIC, convergence_case, random_small)
+                       FRIC_QUADRATIC, convergence_case, random_small, rossby_case, rotate_ccw,
+                       unrotate_ccw)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 RNG = np.random.default_rng(1234)
@@ -364,6 +365,44 @@ def test_north_vector_invariance():
     r0 = O.Oracle(wl0).run(nsteps=20, dts=dts)[0]
     for a, b in zip(r1, r0):
         assert rel_err(a, b) <= 1e-13
+
+
+def test_beta_plane_quarter_turn_exact():
+    """eq. betaplane with the north vector turned with the grid: the
+    quarter-turned problem (f gradient, momenta and north angle turned
+    together) gives the quarter-turned solution to roundoff."""
+    wl = rossby_case(N=40, theta_deg=0.0, amp=0.5, sigma_cells=6.0, dx=40e3)
+    dts = O.Oracle(wl).run(nsteps=60)[2]
+    ref = O.Oracle(wl).run(nsteps=60, dts=dts)[0]
+    rot = O.Oracle(rotate_ccw(wl)).run(nsteps=60, dts=dts)[0]
+    e = unrotate_ccw(rot[0])
+    u = unrotate_ccw(rot[2])      # (hu', hv') = (-hv, hu)  ->  hu = hv'
+    v = -unrotate_ccw(rot[1])     #                             hv = -hu'
+    assert rel_err(e, ref[0]) <= 1e-12
+    assert rel_err(u, ref[1]) <= 1e-12 and rel_err(v, ref[2]) <= 1e-12
+
+
+@pytest.mark.parametrize("theta", [0.0, 30.0, 90.0])
+def test_beta_plane_eddy_drifts_west(theta):
+    """Section "Coriolis force", Figure varying_north: a geostrophic eddy on a
+    beta plane drifts west (against the local east vector e = (cos theta,
+    -sin theta)), and the drift does not depend on how the grid is oriented
+    against north.  Long Rossby waves move at about beta R_d^2 (1.5 m/s here,
+    R_d = sqrt(gH)/f = 277 km); an eddy of radius ~R_d drifts slower.  After
+    two days the centre of the positive anomaly has moved 2.5-6 cells
+    (50-120 km) west, within 5 degrees of -e."""
+    wl = rossby_case(N=100, theta_deg=theta, steps=0)
+    st = O.Oracle(wl).run(nsteps=1700)[0]
+    e = st[0]
+    X, Y = np.meshgrid(np.arange(100) + 0.5, np.arange(100) + 0.5)
+    w = np.clip(e, 0.0, None) * (np.hypot(X - 50, Y - 50) < 30)
+    sx, sy = (w * X).sum() / w.sum() - 50, (w * Y).sum() / w.sum() - 50
+    th = np.deg2rad(theta)
+    west = np.array([-np.cos(th), np.sin(th)])
+    along = sx * west[0] + sy * west[1]
+    across = -sx * west[1] + sy * west[0]
+    assert 2.5 <= along <= 6.0
+    assert abs(np.degrees(np.arctan2(across, along))) <= 5.0
 
 
 # --------------------------------------------------------------------------

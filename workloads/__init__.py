@@ -24,4 +24,7 @@ from .configs import (  # noqa: F401
     convergence_case,
     perimeter_len,
     random_small,
+    rossby_case,
+    rotate_ccw,
+    unrotate_ccw,
 )

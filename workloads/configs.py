@@ -379,6 +379,62 @@ def convergence_case(N: int, L_km: float = 500.0, c_km: float = 300.0,
     )
 
 
+def rossby_case(N: int = 350, theta_deg: float = 0.0, dx: float = 20e3, H: float = 50.0,
+                f_ref: float = 8e-5, beta: float = 2e-11, amp: float = 0.5, sigma_cells: float = 15.0,
+                steps: int = 300) -> Workload:
+    """Planetary Rossby waves on a beta plane (section "Coriolis force", eq.
+    betaplane): N x N cells of dx, flat depth H, walls, north vector
+    n = (sin theta, cos theta) the same in every cell, f = f_ref + beta n.(x -
+    x_ref) with x_ref the domain centre, and a Gaussian bump in geostrophic
+    balance with the local f at the centre (f v = g d(eta)/dx, f u =
+    -g d(eta)/dy, momenta H u, H v).  f_ref = 8e-5 reads the printed 8e-4 as
+    2 omega sin 33 deg."""
+    X, Y = _cell_centres(N, N, dx, dx)
+    xr = yr = 0.5 * N * dx
+    th = np.deg2rad(theta_deg)
+    nxv, nyv = np.sin(th), np.cos(th)
+    f = f_ref + beta * (nxv * (X - xr) + nyv * (Y - yr))
+    s2 = (sigma_cells * dx) ** 2
+    rx, ry = X - xr, Y - yr
+    eta = amp * np.exp(-(rx * rx + ry * ry) / (2.0 * s2))
+    detadx = -rx / s2 * eta
+    detady = -ry / s2 * eta
+    u = -G * detady / f
+    v = G * detadx / f
+    return Workload(
+        name=f"rossby_{N}_theta{theta_deg:g}",
+        nx=N, ny=N, dx=dx, dy=dx,
+        Hc=_f32(np.full((N + 1, N + 1), H)), f=_f32(f), north=_f32(np.full((N, N), th)),
+        eta=_f32(eta), hu=_f32(H * u), hv=_f32(H * v),
+        courant=0.45, steps=steps,
+    )
+
+
+def rotate_ccw(wl: Workload) -> Workload:
+    """The same problem turned a quarter turn counter-clockwise: the cell at
+    (x, y) moves to (Ly - y, x), momenta (hu, hv) -> (-hv, hu), north angles
+    minus 90 degrees, sides W, E, S, N -> S, N, E, W.  Input arrays only."""
+    def r(a):
+        return None if a is None else np.ascontiguousarray(np.asarray(a).T[:, ::-1])
+    if wl.bnd is not None:
+        raise ValueError("rotate_ccw: nested boundary data is not rotated")
+    W, E, S, Nn = wl.bc
+    tau = np.asarray(wl.wind_tau)
+    return wl.copy(
+        name=wl.name + "_rot",
+        nx=wl.ny, ny=wl.nx, dx=wl.dy, dy=wl.dx,
+        Hc=r(wl.Hc), f=r(wl.f), north=None if wl.north is None else _f32(r(wl.north) - np.pi / 2),
+        eta=r(wl.eta), hu=_f32(-r(wl.hv)), hv=r(wl.hu),
+        land=r(wl.land), bc=(S, Nn, E, W),
+        wind_tau=_f32(np.stack([-tau[:, 1], tau[:, 0]], axis=1)),
+    )
+
+
+def unrotate_ccw(a: np.ndarray) -> np.ndarray:
+    """Inverse of the array map of rotate_ccw for a scalar field."""
+    return np.ascontiguousarray(np.asarray(a)[:, ::-1].T)
+
+
 def random_small(nx: int, ny: int, seed: int, bc=(BC_WALL,) * 4, friction=FRIC_NONE,
                  friction_coeff=0.0, land_frac: float = 0.0, wet_dry: bool = False,
                  wind=(0.0, 0.0), north_random: bool = True, depth=(20.0, 400.0),

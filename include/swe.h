@@ -116,6 +116,23 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
 int swe_set_forcing(swe_domain *d, int32_t kind, int32_t n_times, const double *times,
                     const float *data);
 
+/* Wind at 10 m on its own grid (section "Wind"): n_times snapshots at
+ * increasing times of ny_w x nx_w samples of (u, v) in m/s, laid out
+ * [n_times][ny_w][nx_w][2].  The samples sit at the centres of an nx_w x ny_w
+ * partition of the domain; each stage interpolates them bilinearly in space
+ * (held at the edge samples outside their hull) and linearly in time (eq.
+ * windstress_interpol; clamped outside the snapshot times), then adds the
+ * stress of Large and Pond, (rho_air / rho_w) C_D |W| W with C_D = 1.2e-3
+ * below 11 m/s and (0.49 + 0.065 |W|) 1e-3 above, to the momentum equations
+ * (on top of any stress from swe_set_forcing).  The data is copied into
+ * dev_buffer: caller-owned device memory of swe_wind_field_bytes bytes,
+ * 256-byte aligned, borrowed until the field is replaced or removed
+ * (n_times = 0) or the domain destroyed.  Synchronises.  Errors: SWE_E_ARG,
+ * SWE_E_NOMEM (buffer too small), SWE_E_STATE inside an ensemble. */
+int swe_wind_field_bytes(int32_t n_times, int32_t nx_w, int32_t ny_w, size_t *bytes);
+int swe_set_wind_field(swe_domain *d, int32_t n_times, int32_t nx_w, int32_t ny_w, const double *times,
+                       const float *w10, double rho_air, void *dev_buffer, size_t bytes);
+
 /* Advance n_steps SSP-RK2 steps (eq. rk2_semiimp with the spatial operator of
  * eq. sw_semidiscrete), each with the dt of eq. cfl computed on the device
  * from the state at the start of the step.  Asynchronous: no host

@@ -45,6 +45,8 @@ class _Params(C.Structure):
         ("rho_w", C.c_double), ("frs_width", C.c_int32), ("frs_d0", C.c_double),
         ("wind_n", C.c_int32), ("wind_t", _D), ("wind_tau", _D),
         ("bnd_n", C.c_int32), ("bnd_t", _D), ("bnd", _D),
+        ("w10_n", C.c_int32), ("w10_nx", C.c_int32), ("w10_ny", C.c_int32),
+        ("w10_t", _D), ("w10", _D), ("rho_a", C.c_double),
     ]
 
 
@@ -146,6 +148,13 @@ class Oracle:
             p.bnd_n, p.bnd_t, p.bnd = len(bt), _dp(bt), _dp(bd)
         else:
             p.bnd_n = 0
+        w10 = getattr(wl, "w10", None)
+        if w10 is not None:
+            wt = self._hold("w10_t", _f64(wl.w10_t))
+            wd = self._hold("w10", _f64(w10))
+            p.w10_n, p.w10_ny, p.w10_nx = wd.shape[0], wd.shape[1], wd.shape[2]
+            p.w10_t, p.w10 = _dp(wt), _dp(wd)
+        p.rho_a = float(getattr(wl, "rho_a", 1.225))
         self.p = p
         s = _Static()
         s.Hc, s.f, s.north = _dp(self.Hc), _dp(self.f), _dp(self.north)

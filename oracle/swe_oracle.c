@@ -125,6 +125,52 @@ static void wind_at(const or_params *p, double tau, double *tx, double *ty)
     *ty = (1.0 - s) * p->wind_tau[2 * k + 1] + s * p->wind_tau[2 * (k + 1) + 1];
 }
 
+/* Wind at 10 m from its own grid (section "Wind"): linear in time between
+ * the two snapshots around tau (eq. windstress_interpol), bilinear in space
+ * with the samples at the centres of a w10_nx x w10_ny partition of the
+ * domain and clamped at its edges (what a texture fetch with linear
+ * filtering returns), then the stress of Large and Pond,
+ *   tau / rho_w = (rho_a / rho_w) C_D |W| W,
+ *   C_D = 1.2e-3 for |W| < 11 m/s, (0.49 + 0.065 |W|) 1e-3 above,
+ * returned as the kinematic source of the momentum equations. */
+static double w10_sample(const or_params *p, int snap, double gx, double gy, int comp)
+{
+    const int nxw = p->w10_nx, nyw = p->w10_ny;
+    if (gx < 0.0) gx = 0.0;
+    if (gx > nxw - 1) gx = nxw - 1;
+    if (gy < 0.0) gy = 0.0;
+    if (gy > nyw - 1) gy = nyw - 1;
+    int i0 = (int)floor(gx), j0 = (int)floor(gy);
+    int i1 = i0 + 1 < nxw ? i0 + 1 : nxw - 1, j1 = j0 + 1 < nyw ? j0 + 1 : nyw - 1;
+    double fx = gx - i0, fy = gy - j0;
+    const double *W = p->w10 + (size_t)snap * nxw * nyw * 2;
+#define WS(i, j) W[((size_t)(j) * nxw + (i)) * 2 + comp]
+    double south = (1.0 - fx) * WS(i0, j0) + fx * WS(i1, j0);
+    double north = (1.0 - fx) * WS(i0, j1) + fx * WS(i1, j1);
+#undef WS
+    return (1.0 - fy) * south + fy * north;
+}
+
+static void w10_stress(const or_params *p, int i, int j, double tau, double *sx, double *sy)
+{
+    *sx = *sy = 0.0;
+    if (p->w10_n <= 0 || !p->w10) return;
+    int k; double s;
+    time_weights(p->w10_n, p->w10_t, tau, &k, &s);
+    int kb = p->w10_n > 1 ? k + 1 : k;
+    /* cell centre in wind-grid sample coordinates */
+    double gx = (i + 0.5) * p->w10_nx / (double)p->nx - 0.5;
+    double gy = (j + 0.5) * p->w10_ny / (double)p->ny - 0.5;
+    double W[2];
+    for (int c = 0; c < 2; ++c)
+        W[c] = (1.0 - s) * w10_sample(p, k, gx, gy, c) + s * w10_sample(p, kb, gx, gy, c);
+    double speed = sqrt(W[0] * W[0] + W[1] * W[1]);
+    double cd = speed < 11.0 ? 1.2e-3 : (0.49 + 0.065 * speed) * 1e-3;
+    double q = p->rho_a / p->rho_w * cd * speed;
+    *sx = q * W[0];
+    *sy = q * W[1];
+}
+
 /* external state at perimeter position idx (W: row, E: ny+row, S: 2ny+col,
  * N: 2ny+nx+col) for field fld (0 eta, 1 hu, 2 hv) at time tau */
 static double ext_at(const or_params *p, int idx, int fld, double tau)
@@ -194,6 +240,7 @@ static int check_params(const or_params *p)
         if (p->bc[k] < 0 || p->bc[k] > 2) return -1;
         if (p->bc[k] == OR_BC_NESTED && (p->bnd_n < 1 || !p->bnd || !p->bnd_t)) return -1;
     }
+    if (p->w10_n > 0 && (p->w10_nx < 1 || p->w10_ny < 1 || !p->w10 || !p->w10_t || !(p->rho_a > 0))) return -1;
     return 0;
 }
 
@@ -445,10 +492,12 @@ static void compute_rhs(const or_params *p, const or_static *s, ws_t *w, const d
             double Cx = w->f[b] * (c * hvn - sn * hue);
             double Cy = w->f[b] * (-sn * hvn - c * hue);
             Me[o] = -(w->F[0][b] - w->F[0][bw]) / p->dx - (w->G[0][b] - w->G[0][bs]) / p->dy;
+            double wsx, wsy;
+            w10_stress(p, i, j, tau, &wsx, &wsy);
             Mu[o] = -(w->F[1][b] - w->F[1][bw]) / p->dx - (w->G[1][b] - w->G[1][bs]) / p->dy +
-                    g / (2.0 * p->dx) * (hE + hW) * (HE - HW) + Cx + tx / p->rho_w;
+                    g / (2.0 * p->dx) * (hE + hW) * (HE - HW) + Cx + tx / p->rho_w + wsx;
             Mv[o] = -(w->F[2][b] - w->F[2][bw]) / p->dx - (w->G[2][b] - w->G[2][bs]) / p->dy +
-                    g / (2.0 * p->dy) * (hN + hS) * (HN - HS) + Cy + ty / p->rho_w;
+                    g / (2.0 * p->dy) * (hN + hS) * (HN - HS) + Cy + ty / p->rho_w + wsy;
         }
 }
 

@@ -10,7 +10,8 @@
  *
  * Arrays: cell fields [ny][nx] (x fastest), corner depths [ny+1][nx+1],
  * boundary snapshots [n][3][2ny+2nx] (W strip by row, E strip, S strip by
- * column, N strip), wind snapshots [n][2] in N/m^2.  All in float64.
+ * column, N strip), wind snapshots [n][2] in N/m^2, optional gridded wind at
+ * 10 m [n][ny_w][nx_w][2] in m/s.  All in float64.
  */
 #ifndef SWE_ORACLE_H
 #define SWE_ORACLE_H
@@ -40,6 +41,11 @@ typedef struct {
     const double *wind_t, *wind_tau;
     int32_t bnd_n;      /* 0 if no nested side */
     const double *bnd_t, *bnd;
+    /* wind at 10 m on its own grid (section "Wind"): w10_n snapshots of
+     * w10_ny x w10_nx samples of (u, v) in m/s, [n][ny][nx][2]; 0 = none */
+    int32_t w10_n, w10_nx, w10_ny;
+    const double *w10_t, *w10;
+    double rho_a;       /* density of air */
 } or_params;
 
 /* per-cell inputs of the problem statement */

@@ -486,6 +486,59 @@ int swe_set_forcing(swe_domain *d, int32_t kind, int32_t n_times, const double *
     return SWE_OK;
 }
 
+int swe_wind_field_bytes(int32_t n_times, int32_t nx_w, int32_t ny_w, size_t *bytes)
+{
+    if (!bytes || n_times < 1 || nx_w < 1 || ny_w < 1 || (int64_t)nx_w * ny_w > ((int64_t)1 << 26))
+        return fail(SWE_E_ARG, "bad wind-field size");
+    *bytes = align_up((size_t)n_times * sizeof(double), kAlign) + (size_t)n_times * nx_w * ny_w * 2 * sizeof(float);
+    return SWE_OK;
+}
+
+int swe_set_wind_field(swe_domain *d, int32_t n_times, int32_t nx_w, int32_t ny_w, const double *times,
+                       const float *w10, double rho_air, void *dev_buffer, size_t bytes)
+{
+    if (!d) return fail(SWE_E_ARG, "domain is NULL");
+    if (d->ensemble) return fail(SWE_E_STATE, "domain belongs to an ensemble");
+    if (n_times == 0) {
+        d->dom.w10n = 0;
+        return SWE_OK;
+    }
+    size_t need = 0;
+    int rc = swe_wind_field_bytes(n_times, nx_w, ny_w, &need);
+    if (rc) return rc;
+    if (!times || !w10 || !dev_buffer) return fail(SWE_E_ARG, "NULL argument");
+    if (((uintptr_t)dev_buffer) % kAlign) return fail(SWE_E_ARG, "wind buffer must be 256-byte aligned");
+    if (bytes < need) return fail(SWE_E_NOMEM, "wind buffer too small");
+    if (!(std::isfinite(rho_air) && rho_air > 0)) return fail(SWE_E_ARG, "rho_air must be > 0");
+    for (int k = 0; k < n_times; ++k) {
+        if (!std::isfinite(times[k])) return fail(SWE_E_ARG, "non-finite wind time");
+        if (k > 0 && !(times[k] > times[k - 1])) return fail(SWE_E_ARG, "wind times must increase");
+    }
+    const size_t nv = (size_t)n_times * nx_w * ny_w * 2;
+    if (!all_finite(w10, nv)) return fail(SWE_E_ARG, "non-finite wind");
+    char *b = (char *)dev_buffer;
+    const size_t toff = align_up((size_t)n_times * sizeof(double), kAlign);
+    HIP_TRY(hipMemcpyAsync(b, times, (size_t)n_times * sizeof(double), hipMemcpyHostToDevice, d->stream));
+    {
+        Uploader up(d->stream, nv * sizeof(float));
+        hipError_t e;
+        // rows of one sample line (nx_w (u, v) pairs), contiguous on the device
+        if ((e = up.plane(b + toff, 2 * nx_w, w10, 2 * nx_w, n_times * ny_w)) || (e = up.flush()))
+            return hip_fail(e, "wind upload");
+    }
+    Dom &D = d->dom;
+    D.w10_t = (const double *)b;
+    D.w10 = (const float *)(b + toff);
+    D.w10nx = nx_w;
+    D.w10ny = ny_w;
+    D.w10sx = (float)((double)nx_w / d->p.nx);
+    D.w10sy = (float)((double)ny_w / d->p.ny);
+    D.w10q = (float)(rho_air / d->p.rho_w);
+    D.w10n = n_times;
+    drop_graphs(d);  // the graphs hold the domain block by value
+    return SWE_OK;
+}
+
 int swe_step(swe_domain *d, int32_t n_steps)
 {
     int rc = check_ready(d);

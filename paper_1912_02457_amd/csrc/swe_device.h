@@ -77,6 +77,11 @@ struct Dom {
     int nw;                        // wind snapshots
     const double *wind_t;
     const float *wind;             // [nw][2]
+    int w10n, w10nx, w10ny;        // wind at 10 m on its own grid: snapshots, samples (0 = none)
+    float w10sx, w10sy;            // samples per cell along x and y
+    float w10q;                    // rho_air / rho_w
+    const double *w10_t;
+    const float *w10;              // [w10n][w10ny][w10nx][2] m/s
     Ctrl *ctrl;
     double *partials;              // diagnostics partial sums
 };

@@ -14,7 +14,7 @@
 namespace swe {
 hipError_t launch_stage(int stage, bool proj, const Dom &d, const Tiling &T, int parity, double dt_fixed,
                         hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
-hipError_t launch_ensemble(int stage, bool proj, const EnsMember *mem, const EnsItem *items, EnsCtrl *ec,
+hipError_t launch_ensemble(int stage, bool proj, bool w10, const EnsMember *mem, const EnsItem *items, EnsCtrl *ec,
                            int parity, int chunk, int nblocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_cfl(const Dom &d, int slot, hipStream_t s);
 hipError_t launch_ctrl_reset(Ctrl *c, double t, int slot, hipStream_t s);

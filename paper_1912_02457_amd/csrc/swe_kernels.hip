@@ -347,7 +347,42 @@ struct TileCtx {
     float dt, wx, wy;
     int bk;          // boundary snapshot interval and weight at the stage time
     double bs;
+    int wk;          // wind-field snapshot interval and weight at the stage time
+    float ws;
 };
+
+// Wind at 10 m from its own grid at cell (i, o): samples at the centres of a
+// w10nx x w10ny partition of the domain, bilinear in space (clamped at the
+// edges, as a texture fetch with linear filtering) and linear in time between
+// the snapshots around the stage time (eq. windstress_interpol); then the
+// stress of Large and Pond, rho_a/rho_w C_D |W| W with C_D = 1.2e-3 below
+// 11 m/s and (0.49 + 0.065 |W|) 1e-3 above, as the kinematic source.
+__device__ __forceinline__ void w10_stress(const Dom &d, const TileCtx &c, float &sx, float &sy)
+{
+    float gx = fminf(fmaxf(((float)c.i + 0.5f) * d.w10sx - 0.5f, 0.f), (float)(d.w10nx - 1));
+    float gy = fminf(fmaxf(((float)c.o + 0.5f) * d.w10sy - 0.5f, 0.f), (float)(d.w10ny - 1));
+    const int i0 = (int)gx, j0 = (int)gy;
+    const int i1 = min(i0 + 1, d.w10nx - 1), j1 = min(j0 + 1, d.w10ny - 1);
+    const float fx = gx - (float)i0, fy = gy - (float)j0;
+    const uint32_t plane = (uint32_t)d.w10nx * (uint32_t)d.w10ny * 2u;
+    const float *Wa = d.w10 + (uint32_t)c.wk * plane;
+    const float *Wb = d.w10n > 1 ? Wa + plane : Wa;
+    float W[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        auto at = [&](const float *P, int i, int j) { return P[((uint32_t)j * (uint32_t)d.w10nx + (uint32_t)i) * 2u + q]; };
+        float a = (1.f - fy) * ((1.f - fx) * at(Wa, i0, j0) + fx * at(Wa, i1, j0)) +
+                  fy * ((1.f - fx) * at(Wa, i0, j1) + fx * at(Wa, i1, j1));
+        float b = (1.f - fy) * ((1.f - fx) * at(Wb, i0, j0) + fx * at(Wb, i1, j0)) +
+                  fy * ((1.f - fx) * at(Wb, i0, j1) + fx * at(Wb, i1, j1));
+        W[q] = (1.f - c.ws) * a + c.ws * b;
+    }
+    const float sp = fsqrt(W[0] * W[0] + W[1] * W[1]);
+    const float cd = sp < 11.f ? 1.2e-3f : (0.49f + 0.065f * sp) * 1e-3f;
+    const float k = d.w10q * cd * sp;
+    sx = k * W[0];
+    sy = k * W[1];
+}
 
 // Flow relaxation (eq. frs) of one output cell, split so that its loads are
 // issued at the start of the row and consumed at the end: the nearest nested
@@ -390,7 +425,7 @@ __device__ __forceinline__ FrsPre frs_prefetch(const Dom &d, const TileCtx &c)
 // x-direction reconstruction and flux of the output row A, the update of
 // eq. rk2_semiimp and (stage 2) the flow relaxation and CFL reduction.
 // Every lane takes part in the cross-lane exchanges; only output lanes store.
-template <int STAGE, bool PROJ, bool FRS>
+template <int STAGE, bool PROJ, bool FRS, bool W10>
 __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 &Gn, const TileCtx &c,
                                            float e0, float u0, float v0, const FrsPre &fp, const Dom &d,
                                            float &wmax_loc, int &bad)
@@ -429,11 +464,18 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
         Cx = A.f * A.v;
         Cy = -A.f * A.u;
     }
+    float wx = c.wx, wy = c.wy;
+    if (W10 && d.w10n > 0) {
+        float sx, sy;
+        w10_stress(d, c, sx, sy);
+        wx += sx;
+        wy += sy;
+    }
     float Me = -(Fe.e - Fwe) * d.rdx - (Gn.e - Gs.e) * d.rdy;
     float Mu = -(Fe.p - Fwp) * d.rdx - (Gn.q - Gs.q) * d.rdy + bathy_source(eE, eW, A.He, A.Hw, d) * d.rdx +
-               Cx + c.wx;
+               Cx + wx;
     float Mv = -(Fe.q - Fwq) * d.rdx - (Gn.p - Gs.p) * d.rdy +
-               bathy_source(A.eN, A.eS, A.Hn, A.Hs, d) * d.rdy + Cy + c.wy;
+               bathy_source(A.eN, A.eS, A.Hn, A.Hs, d) * d.rdy + Cy + wy;
     const uint32_t oo = (uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i;
     const float dt = c.dt;
     float S = friction_coeff(d, A.ri, A.u, A.v);
@@ -553,7 +595,7 @@ __device__ __forceinline__ RawRow load_row(const Dom &d, const float *__restrict
     return w;
 }
 
-template <int STAGE, bool PROJ, bool GHOST, bool FRS>
+template <int STAGE, bool PROJ, bool GHOST, bool FRS, bool W10>
 __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1, float &wmax_loc, int &bad)
 {
     const float *__restrict__ E = STAGE == 1 ? d.eta : d.eta1;
@@ -635,7 +677,7 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
         F3 Gn = y_flux(A, B, us, vs, d);
         // a row whose output cells are all land has nothing to update
         if (__ballot(c.out_lane && !A.land) != 0)
-            finish_row<STAGE, PROJ, FRS>(A, Gs, Gn, c, e0, u0, v0, fp, d, wmax_loc, bad);
+            finish_row<STAGE, PROJ, FRS, W10>(A, Gs, Gn, c, e0, u0, v0, fp, d, wmax_loc, bad);
         Gs = Gn;
     };
     for (int k = y0 + 2;;) {
@@ -699,7 +741,7 @@ __device__ __forceinline__ void advance_ctrl(Ctrl *ctrl, const StepTime &s, int 
 //            then flow relaxation (eq. frs) and the CFL reduction for the
 //            next step (eq. cfl)
 // eq. rk2_semiimp; M is eq. sw_semidiscrete with the sources of eq. swe.
-template <int STAGE, bool PROJ>
+template <int STAGE, bool PROJ, bool W10>
 __device__ __forceinline__ void process_tile(const Dom &d, const Tiling &T, int tile, int parity, const StepTime &st,
                                              int lane)
 {
@@ -710,6 +752,13 @@ __device__ __forceinline__ void process_tile(const Dom &d, const Tiling &T, int 
     c.bs = 0.0;
     if (d.nb > 0) time_weights(d.nb, d.bnd_t, tau, c.bk, c.bs);
     wind_at(d, tau, c.wx, c.wy);
+    c.wk = 0;
+    c.ws = 0.f;
+    if (d.w10n > 0) {
+        double s;
+        time_weights(d.w10n, d.w10_t, tau, c.wk, s);
+        c.ws = (float)s;
+    }
 
     const int nx = d.nx, ny = d.ny;
     int strip, rb;
@@ -735,10 +784,10 @@ __device__ __forceinline__ void process_tile(const Dom &d, const Tiling &T, int 
     }
     float wmax_loc = 0.f;
     int bad = 0;
-    if (!ghost && !frs) run_tile<STAGE, PROJ, false, false>(d, c, y0, y1, wmax_loc, bad);
-    else if (!ghost) run_tile<STAGE, PROJ, false, true>(d, c, y0, y1, wmax_loc, bad);
-    else if (!frs) run_tile<STAGE, PROJ, true, false>(d, c, y0, y1, wmax_loc, bad);
-    else run_tile<STAGE, PROJ, true, true>(d, c, y0, y1, wmax_loc, bad);
+    if (!ghost && !frs) run_tile<STAGE, PROJ, false, false, W10>(d, c, y0, y1, wmax_loc, bad);
+    else if (!ghost) run_tile<STAGE, PROJ, false, true, W10>(d, c, y0, y1, wmax_loc, bad);
+    else if (!frs) run_tile<STAGE, PROJ, true, false, W10>(d, c, y0, y1, wmax_loc, bad);
+    else run_tile<STAGE, PROJ, true, true, W10>(d, c, y0, y1, wmax_loc, bad);
 
     if (STAGE == 2) {
         wmax_loc = wave_max(wmax_loc);
@@ -753,7 +802,7 @@ __device__ __forceinline__ void process_tile(const Dom &d, const Tiling &T, int 
 // ---------------------------------------------------------------------------
 // single-domain stage kernel: one wavefront per tile
 // ---------------------------------------------------------------------------
-template <int STAGE, bool PROJ>
+template <int STAGE, bool PROJ, bool W10>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Tiling T, int parity,
                                                                       double dt_fixed)
 {
@@ -771,7 +820,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Ti
     const StepTime st = step_time(d, parity, dt_fixed, lane);
     if (STAGE == 1 && b == 0 && wid == 0) advance_ctrl(d.ctrl, st, parity, lane);
     if (st.skip || tile >= T.ntiles) return;
-    process_tile<STAGE, PROJ>(d, T, tile, parity, st, lane);
+    process_tile<STAGE, PROJ, W10>(d, T, tile, parity, st, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -781,7 +830,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Ti
 // chunks taken with one atomicAdd each, until the partition is exhausted.
 // Every member has its own parameters, time, dt slot and CFL accumulator.
 // ---------------------------------------------------------------------------
-template <int STAGE, bool PROJ>
+template <int STAGE, bool PROJ, bool W10>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) void ensemble_kernel(const EnsMember *__restrict__ mem,
                                                                          const EnsItem *__restrict__ items,
                                                                          EnsCtrl *ec, int parity, int chunk)
@@ -809,7 +858,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void ensemble_kernel(const 
             const int p = parity ^ M.pflip;
             const StepTime st = step_time(M.d, p, 0.0, lane);
             if (STAGE == 1 && it.tile == 0) advance_ctrl(M.d.ctrl, st, p, lane);
-            if (!st.skip) process_tile<STAGE, PROJ>(M.d, M.T, it.tile, p, st, lane);
+            if (!st.skip) process_tile<STAGE, PROJ, W10>(M.d, M.T, it.tile, p, st, lane);
         }
     }
 }
@@ -935,28 +984,33 @@ __global__ __launch_bounds__(kDiagThreads) void diag_final_kernel(Dom d)
 // ---------------------------------------------------------------------------
 // launch wrappers (host side)
 // ---------------------------------------------------------------------------
-hipError_t launch_stage(int stage, bool proj, const Dom &d, const Tiling &T, int parity,
-                        double dt_fixed, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+// Kernel variants: stage (1, 2) x literal north projection x gridded wind.
+// The wind-field code is compiled only into the W10 variants (it would
+// otherwise raise the register count of every launch).
+template <int S, bool P, bool W>
+hipError_t launch_stage_v(const Dom &d, const Tiling &T, int parity, double dt_fixed, hipStream_t s, hipEvent_t ev0,
+                          hipEvent_t ev1)
 {
     dim3 grid(T.nblocks), block(kWave * kWavesPerBlock);
-    if (ev0) {
-        if (stage == 1) {
-            if (proj) hipExtLaunchKernelGGL(stage_kernel<1, true>, grid, block, 0, s, ev0, ev1, 0, d, T, parity, dt_fixed);
-            else hipExtLaunchKernelGGL(stage_kernel<1, false>, grid, block, 0, s, ev0, ev1, 0, d, T, parity, dt_fixed);
-        } else {
-            if (proj) hipExtLaunchKernelGGL(stage_kernel<2, true>, grid, block, 0, s, ev0, ev1, 0, d, T, parity, dt_fixed);
-            else hipExtLaunchKernelGGL(stage_kernel<2, false>, grid, block, 0, s, ev0, ev1, 0, d, T, parity, dt_fixed);
-        }
-    } else {
-        if (stage == 1) {
-            if (proj) stage_kernel<1, true><<<grid, block, 0, s>>>(d, T, parity, dt_fixed);
-            else stage_kernel<1, false><<<grid, block, 0, s>>>(d, T, parity, dt_fixed);
-        } else {
-            if (proj) stage_kernel<2, true><<<grid, block, 0, s>>>(d, T, parity, dt_fixed);
-            else stage_kernel<2, false><<<grid, block, 0, s>>>(d, T, parity, dt_fixed);
-        }
-    }
+    if (ev0) hipExtLaunchKernelGGL(stage_kernel<S, P, W>, grid, block, 0, s, ev0, ev1, 0, d, T, parity, dt_fixed);
+    else stage_kernel<S, P, W><<<grid, block, 0, s>>>(d, T, parity, dt_fixed);
     return hipGetLastError();
+}
+
+hipError_t launch_stage(int stage, bool proj, const Dom &d, const Tiling &T, int parity, double dt_fixed,
+                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    const bool w = d.w10n > 0;
+    switch ((stage == 2 ? 4 : 0) | (proj ? 2 : 0) | (w ? 1 : 0)) {
+    case 0: return launch_stage_v<1, false, false>(d, T, parity, dt_fixed, s, ev0, ev1);
+    case 1: return launch_stage_v<1, false, true>(d, T, parity, dt_fixed, s, ev0, ev1);
+    case 2: return launch_stage_v<1, true, false>(d, T, parity, dt_fixed, s, ev0, ev1);
+    case 3: return launch_stage_v<1, true, true>(d, T, parity, dt_fixed, s, ev0, ev1);
+    case 4: return launch_stage_v<2, false, false>(d, T, parity, dt_fixed, s, ev0, ev1);
+    case 5: return launch_stage_v<2, false, true>(d, T, parity, dt_fixed, s, ev0, ev1);
+    case 6: return launch_stage_v<2, true, false>(d, T, parity, dt_fixed, s, ev0, ev1);
+    default: return launch_stage_v<2, true, true>(d, T, parity, dt_fixed, s, ev0, ev1);
+    }
 }
 
 // waves per SIMD that one stage kernel variant can keep resident, from its
@@ -965,48 +1019,49 @@ int stage_waves_per_simd(int stage, bool proj)
 {
     hipFuncAttributes a{};
     hipError_t e;
-    if (stage == 1) e = proj ? hipFuncGetAttributes(&a, (const void *)stage_kernel<1, true>)
-                             : hipFuncGetAttributes(&a, (const void *)stage_kernel<1, false>);
-    else e = proj ? hipFuncGetAttributes(&a, (const void *)stage_kernel<2, true>)
-                  : hipFuncGetAttributes(&a, (const void *)stage_kernel<2, false>);
+    if (stage == 1) e = proj ? hipFuncGetAttributes(&a, (const void *)stage_kernel<1, true, false>)
+                             : hipFuncGetAttributes(&a, (const void *)stage_kernel<1, false, false>);
+    else e = proj ? hipFuncGetAttributes(&a, (const void *)stage_kernel<2, true, false>)
+                  : hipFuncGetAttributes(&a, (const void *)stage_kernel<2, false, false>);
     if (e != hipSuccess || a.numRegs <= 0) return 3;
     int regs = (a.numRegs + 7) / 8 * 8;
     int w = 512 / regs;
     return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
-hipError_t launch_ensemble(int stage, bool proj, const EnsMember *mem, const EnsItem *items, EnsCtrl *ec,
-                           int parity, int chunk, int nblocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+template <int S, bool P, bool W>
+hipError_t launch_ensemble_v(const EnsMember *mem, const EnsItem *items, EnsCtrl *ec, int parity, int chunk,
+                             int nblocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     dim3 grid(nblocks), block(kWave * kWavesPerBlock);
-    if (ev0) {
-        if (stage == 1) {
-            if (proj) hipExtLaunchKernelGGL(ensemble_kernel<1, true>, grid, block, 0, s, ev0, ev1, 0, mem, items, ec, parity, chunk);
-            else hipExtLaunchKernelGGL(ensemble_kernel<1, false>, grid, block, 0, s, ev0, ev1, 0, mem, items, ec, parity, chunk);
-        } else {
-            if (proj) hipExtLaunchKernelGGL(ensemble_kernel<2, true>, grid, block, 0, s, ev0, ev1, 0, mem, items, ec, parity, chunk);
-            else hipExtLaunchKernelGGL(ensemble_kernel<2, false>, grid, block, 0, s, ev0, ev1, 0, mem, items, ec, parity, chunk);
-        }
-    } else {
-        if (stage == 1) {
-            if (proj) ensemble_kernel<1, true><<<grid, block, 0, s>>>(mem, items, ec, parity, chunk);
-            else ensemble_kernel<1, false><<<grid, block, 0, s>>>(mem, items, ec, parity, chunk);
-        } else {
-            if (proj) ensemble_kernel<2, true><<<grid, block, 0, s>>>(mem, items, ec, parity, chunk);
-            else ensemble_kernel<2, false><<<grid, block, 0, s>>>(mem, items, ec, parity, chunk);
-        }
-    }
+    if (ev0) hipExtLaunchKernelGGL(ensemble_kernel<S, P, W>, grid, block, 0, s, ev0, ev1, 0, mem, items, ec, parity, chunk);
+    else ensemble_kernel<S, P, W><<<grid, block, 0, s>>>(mem, items, ec, parity, chunk);
     return hipGetLastError();
+}
+
+hipError_t launch_ensemble(int stage, bool proj, bool w10, const EnsMember *mem, const EnsItem *items, EnsCtrl *ec,
+                           int parity, int chunk, int nblocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    switch ((stage == 2 ? 4 : 0) | (proj ? 2 : 0) | (w10 ? 1 : 0)) {
+    case 0: return launch_ensemble_v<1, false, false>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
+    case 1: return launch_ensemble_v<1, false, true>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
+    case 2: return launch_ensemble_v<1, true, false>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
+    case 3: return launch_ensemble_v<1, true, true>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
+    case 4: return launch_ensemble_v<2, false, false>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
+    case 5: return launch_ensemble_v<2, false, true>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
+    case 6: return launch_ensemble_v<2, true, false>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
+    default: return launch_ensemble_v<2, true, true>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
+    }
 }
 
 int ensemble_waves_per_simd(int stage, bool proj)
 {
     hipFuncAttributes a{};
     hipError_t e;
-    if (stage == 1) e = proj ? hipFuncGetAttributes(&a, (const void *)ensemble_kernel<1, true>)
-                             : hipFuncGetAttributes(&a, (const void *)ensemble_kernel<1, false>);
-    else e = proj ? hipFuncGetAttributes(&a, (const void *)ensemble_kernel<2, true>)
-                  : hipFuncGetAttributes(&a, (const void *)ensemble_kernel<2, false>);
+    if (stage == 1) e = proj ? hipFuncGetAttributes(&a, (const void *)ensemble_kernel<1, true, false>)
+                             : hipFuncGetAttributes(&a, (const void *)ensemble_kernel<1, false, false>);
+    else e = proj ? hipFuncGetAttributes(&a, (const void *)ensemble_kernel<2, true, false>)
+                  : hipFuncGetAttributes(&a, (const void *)ensemble_kernel<2, false, false>);
     if (e != hipSuccess || a.numRegs <= 0) return 3;
     int regs = (a.numRegs + 7) / 8 * 8;
     int w = 512 / regs;

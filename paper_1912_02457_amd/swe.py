@@ -72,6 +72,9 @@ SIGNATURES = {
     "swe_init_domain": (C.c_int, [C.POINTER(Params), _VP, C.c_size_t, _VP, C.c_int32, C.c_int32,
                                   _F, _U8, _F, _F, _F, _F, _F, C.POINTER(_VP)]),
     "swe_set_forcing": (C.c_int, [_VP, C.c_int32, C.c_int32, _D, _F]),
+    "swe_wind_field_bytes": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "swe_set_wind_field": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _D, _F, C.c_double, _VP,
+                                     C.c_size_t]),
     "swe_step": (C.c_int, [_VP, C.c_int32]),
     "swe_step_dt": (C.c_int, [_VP, C.c_int32, _D]),
     "swe_run_until": (C.c_int, [_VP, C.c_double, C.POINTER(C.c_int64)]),
@@ -209,6 +212,8 @@ class Domain:
         dom.set_wind(wl.wind_t, wl.wind_tau)
         if wl.bnd is not None:
             dom.set_boundary(wl.bnd_t, wl.bnd)
+        if getattr(wl, "w10", None) is not None:
+            dom.set_wind_field(wl.w10_t, wl.w10, rho_air=getattr(wl, "rho_a", 1.225))
         return dom
 
     # -- forcing -----------------------------------------------------------
@@ -223,6 +228,26 @@ class Domain:
         d = _f32(data, (len(t), 3, 2 * self.ny + 2 * self.nx))
         _check(load_library().swe_set_forcing(self._h, FORCING_BOUNDARY, len(t),
                                               t.ctypes.data_as(_D), _fp(d)))
+
+    def set_wind_field(self, times, w10, rho_air: float = 1.225):
+        """Wind at 10 m on its own grid, array [n_times][ny_w][nx_w][2] in m/s
+        (Large and Pond stress, trilinear interpolation); None removes it."""
+        import torch
+        L = load_library()
+        if w10 is None:
+            _check(L.swe_set_wind_field(self._h, 0, 0, 0, None, None, 1.0, None, 0))
+            self.wind_field = None
+            return
+        t = np.ascontiguousarray(np.asarray(times, dtype=np.float64))
+        w = np.ascontiguousarray(np.asarray(w10, dtype=np.float32))
+        if w.ndim != 4 or w.shape[0] != len(t) or w.shape[3] != 2:
+            raise ValueError("w10 must be [n_times][ny_w][nx_w][2]")
+        n = C.c_size_t()
+        _check(L.swe_wind_field_bytes(len(t), w.shape[2], w.shape[1], C.byref(n)))
+        buf = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        _check(L.swe_set_wind_field(self._h, len(t), w.shape[2], w.shape[1], t.ctypes.data_as(_D), _fp(w),
+                                    float(rho_air), C.c_void_p(buf.data_ptr()), n.value))
+        self.wind_field = buf  # borrowed by the library until replaced
 
     # -- time stepping -----------------------------------------------------
     def step(self, n: int = 1):

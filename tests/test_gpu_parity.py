@@ -11,7 +11,7 @@ import pytest
 
 from oracle import oracle as O
 from tests._parity import assert_parity, parity
-from workloads import (BC_NESTED, BC_PERIODIC, BC_WALL, FRIC_LINEAR, FRIC_MANNING, FRIC_NONE,
+from workloads import (BC_NESTED, BC_PERIODIC, BC_WALL, FRIC_LINEAR, FRIC_MANNING, FRIC_NONE, add_wind_field,
                        FRIC_QUADRATIC, config1, config2, config3, random_small, rossby_case, rotate_ccw,
                        unrotate_ccw)
 
@@ -103,6 +103,32 @@ def test_north_projection_variant():
     ref, t_ref, rep, own = run_both(wl, 30, proj=True)
     assert_parity(rep, ref, wl.land, label="proj dt-replay")
     assert_parity(own, ref, wl.land, label="proj own-dt")
+
+
+@pytest.mark.parametrize("case", ["walls", "nested_land"])
+def test_gridded_wind_matches_oracle(case):
+    """Wind at 10 m on a coarse grid of its own (bilinear in space, linear in
+    time between snapshots, Large and Pond stress with speeds on both sides of
+    the 11 m/s break), 60 steps against the oracle."""
+    if case == "walls":
+        wl = random_small(97, 83, seed=31, friction=FRIC_LINEAR, friction_coeff=2e-3)
+        wl = add_wind_field(wl, 7, 5, [0.0, 60.0], seed=3)
+    else:
+        wl = random_small(120, 70, seed=32, bc=(BC_NESTED, BC_WALL, BC_NESTED, BC_WALL), land_frac=0.15)
+        wl = add_wind_field(wl, 4, 9, [0.0, 30.0, 90.0], mean=(-6.0, 9.0), seed=4)
+    sp = np.hypot(wl.w10[..., 0], wl.w10[..., 1])
+    assert sp.min() < 11.0 < sp.max()
+    _say(f"gridded wind {case}")
+    ref, t_ref, rep, own = run_both(wl, 60)
+    assert_parity(rep, ref, label=f"w10 {case} dt-replay")
+    assert_parity(own, ref, label=f"w10 {case} own-dt")
+    # the field does act: without it the run differs well beyond the tolerance
+    base = wl.copy(w10=None, w10_t=None)
+    d = _dom(base)
+    d.step_dt(O.Oracle(wl).run(nsteps=60)[2])
+    off = d.read_state()
+    d.close()
+    assert parity(off, ref)["hu_l2"] > 5e-4
 
 
 @pytest.mark.parametrize("proj", [False, True])

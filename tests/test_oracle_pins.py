@@ -520,6 +520,73 @@ def test_wind_spinup_exact():
     np.testing.assert_allclose(v, exv, rtol=1e-12)
 
 
+# wind at 10 m (section "Wind"): the Large and Pond stress with the printed
+# constants rho_a = 1.225, rho_w = 1025, C_D = 1.2e-3 below 11 m/s and
+# (0.49 + 0.065 |W|) 1e-3 above
+def _large_pond_kinematic(Wx, Wy, rho_a=1.225, rho_w=1025.0):
+    sp = np.hypot(Wx, Wy)
+    cd = np.where(sp < 11.0, 1.2e-3, (0.49 + 0.065 * sp) * 1e-3)
+    return rho_a / rho_w * cd * sp * Wx, rho_a / rho_w * cd * sp * Wy
+
+
+@pytest.mark.parametrize("W", [(8.0, -3.0), (-15.0, 12.0)])
+def test_w10_uniform_field_equals_stress_forcing(W):
+    """A wind field that is the same at every sample is the uniform stress
+    rho_a C_D |W| W of the Large and Pond formula (C_D = 1.2e-3 for the 8.5
+    m/s case, 0.49e-3 + 0.065e-3 * 19.2 for the 19.2 m/s case): the gridded
+    path and the stress path give the same run."""
+    base = _uniform(nx=10, ny=7, hu=0.5, hv=-0.2)
+    w10 = np.empty((1, 3, 4, 2))
+    w10[..., 0], w10[..., 1] = W
+    a = base.copy(w10_t=np.array([0.0]), w10=w10)
+    sx, sy = _large_pond_kinematic(np.array(W[0]), np.array(W[1]))
+    b = base.copy(wind_t=np.array([0.0]), wind_tau=np.array([[float(sx) * 1025.0, float(sy) * 1025.0]]))
+    ra = O.Oracle(a).run(nsteps=20, dt_fixed=5.0)[0]
+    rb = O.Oracle(b).run(nsteps=20, dt_fixed=5.0)[0]
+    for x, y in zip(ra, rb):
+        np.testing.assert_allclose(x, y, rtol=1e-13, atol=1e-16)
+    # and the spin-up is exactly linear in time (RK2 on a constant source)
+    np.testing.assert_allclose(ra[1], 0.5 + float(sx) * 100.0, rtol=1e-13)
+
+
+def test_w10_bilinear_in_space_and_linear_in_time():
+    """Samples sit at the centres of an nx_w x ny_w partition of the domain
+    and are interpolated bilinearly (exact for a field linear in x and y
+    inside the hull of the sample centres) and linearly in time between
+    snapshots (eq. windstress_interpol); the source on a flat lake at rest
+    is the Large and Pond stress of the interpolated wind."""
+    nx, ny, dx = 24, 18, 1000.0
+    base = make_wl(30.0, np.zeros((ny, nx)), dx=dx)
+    nxw, nyw = 6, 4
+    Lx, Ly = nx * dx, ny * dx
+    xs = (np.arange(nxw) + 0.5) * Lx / nxw
+    ys = (np.arange(nyw) + 0.5) * Ly / nyw
+    XS, YS = np.meshgrid(xs, ys)
+
+    def lin(X, Y, a):
+        return (a[0] + a[1] * X / Lx + a[2] * Y / Ly, a[3] - a[4] * X / Lx + a[5] * Y / Ly)
+
+    A, B = (2.0, 9.0, -4.0, 1.0, 6.0, 3.0), (-5.0, 4.0, 12.0, 7.0, -8.0, 2.0)
+    w10 = np.stack([np.stack(lin(XS, YS, A), axis=-1), np.stack(lin(XS, YS, B), axis=-1)])
+    wl = base.copy(w10_t=np.array([100.0, 400.0]), w10=w10)
+    o = O.Oracle(wl)
+    X, Y = np.meshgrid((np.arange(nx) + 0.5) * dx, (np.arange(ny) + 0.5) * dx)
+    inside = (X >= xs[0]) & (X <= xs[-1]) & (Y >= ys[0]) & (Y <= ys[-1])
+    for t, s in ((100.0, 0.0), (175.0, 0.25), (400.0, 1.0), (900.0, 1.0)):
+        M = o.rhs((np.zeros((ny, nx)),) * 3, t=t)
+        wa, wb = lin(X, Y, A), lin(X, Y, B)
+        Wx, Wy = (1 - s) * wa[0] + s * wb[0], (1 - s) * wa[1] + s * wb[1]
+        ex, ey = _large_pond_kinematic(Wx, Wy)
+        np.testing.assert_allclose(M[1][inside], ex[inside], rtol=1e-12)
+        np.testing.assert_allclose(M[2][inside], ey[inside], rtol=1e-12)
+        assert np.all(M[0] == 0.0)
+    # outside the hull the field is held at the edge samples (clamp)
+    M = o.rhs((np.zeros((ny, nx)),) * 3, t=100.0)
+    ex, ey = _large_pond_kinematic(w10[0, 0, 0, 0], w10[0, 0, 0, 1])
+    assert M[1][0, 0] == pytest.approx(float(ex), rel=1e-12)
+    assert M[2][0, 0] == pytest.approx(float(ey), rel=1e-12)
+
+
 def test_inertial_oscillation_rk2_amplification():
     """Coriolis source alone (uniform flow): z = hu + i hv obeys dz/dt = -i f z,
     and SSP-RK2 multiplies z by 1 + lam + lam^2/2, lam = -i f dt, per step."""

@@ -14,6 +14,7 @@ from .configs import (  # noqa: F401
     FRIC_NONE,
     FRIC_QUADRATIC,
     Workload,
+    add_wind_field,
     config1,
     config2,
     config3,

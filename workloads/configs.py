@@ -67,6 +67,10 @@ class Workload:
     wind_tau: np.ndarray = field(default_factory=lambda: np.zeros((1, 2), np.float32))
     bnd_t: Optional[np.ndarray] = None
     bnd: Optional[np.ndarray] = None
+    # wind at 10 m on its own grid: [n][ny_w][nx_w][2] m/s at times w10_t
+    w10_t: Optional[np.ndarray] = None
+    w10: Optional[np.ndarray] = None
+    rho_a: float = 1.225
     steps: int = 1
     dt_fixed: Optional[float] = None
     t_end: Optional[float] = None
@@ -408,6 +412,20 @@ def rossby_case(N: int = 350, theta_deg: float = 0.0, dx: float = 20e3, H: float
         eta=_f32(eta), hu=_f32(H * u), hv=_f32(H * v),
         courant=0.45, steps=steps,
     )
+
+
+def add_wind_field(wl: Workload, nx_w: int, ny_w: int, times, mean=(8.0, 3.0), amp: float = 7.0,
+                   seed: int = 0) -> Workload:
+    """The workload with a smooth random wind at 10 m on an nx_w x ny_w grid
+    (one snapshot per entry of times), speeds around |mean| +- amp m/s."""
+    rng = np.random.default_rng(seed)
+    n = len(times)
+    w = np.empty((n, ny_w, nx_w, 2))
+    for k in range(n):
+        for c in range(2):
+            z = _smooth_noise(rng, (ny_w, nx_w), 1.0) if min(nx_w, ny_w) > 2 else rng.standard_normal((ny_w, nx_w))
+            w[k, :, :, c] = mean[c] + amp * z
+    return wl.copy(w10_t=np.asarray(times, np.float64), w10=_f32(w))
 
 
 def rotate_ccw(wl: Workload) -> Workload:

@@ -37,6 +37,12 @@ MUTANTS = {
     "coriolis_source_sign": ("double Cx = w->f[b] * (c * hvn - sn * hue);", "double Cx = -w->f[b] * (c * hvn - sn * hue);"),
     "desing_kappa_floor": ("double lo = fmin(h * h / (2.0 * kappa) + 0.5 * kappa, kappa);",
                            "double lo = fmin(h * h / (2.0 * kappa), kappa);"),
+    "large_pond_no_strong_wind_branch": ("double cd = speed < 11.0 ? 1.2e-3 : (0.49 + 0.065 * speed) * 1e-3;",
+                                         "double cd = 1.2e-3;"),
+    "wind_time_weights_swapped": ("W[c] = (1.0 - s) * w10_sample(p, k, gx, gy, c) + s * w10_sample(p, kb, gx, gy, c);",
+                                  "W[c] = s * w10_sample(p, k, gx, gy, c) + (1.0 - s) * w10_sample(p, kb, gx, gy, c);"),
+    "wind_samples_at_corners": ("double gx = (i + 0.5) * p->w10_nx / (double)p->nx - 0.5;",
+                                "double gx = (i + 0.5) * (p->w10_nx - 1) / (double)p->nx;"),
 }
 
 

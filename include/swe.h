@@ -288,7 +288,8 @@ typedef struct swe_completion {
     int64_t steps;   /* time steps taken */
     int64_t tick;    /* tick after which it completed */
     int32_t status;  /* SWE_OK; SWE_E_UNSTABLE (non-finite state, stopped early); SWE_E_NOMEM
-                        (its workspace and work queue do not fit even in the empty arena) */
+                        (its workspace and work queue do not fit even in the empty arena);
+                        SWE_E_ARG (its inputs were refused when it was started) */
     int32_t pad;
 } swe_completion;
 

@@ -291,7 +291,16 @@ int admit(swe_server *s)
         if (rc) {
             s->arena.release(off, q->bytes);
             if (grow_bytes) s->arena.release(grow_off, grow_bytes);
-            return rc;
+            shapes.pop_back();
+            if (rc == SWE_E_HIP) return rc;  // a runtime failure stops the server
+            // the request itself was refused (its inputs): report it, go on
+            swe_completion c{};
+            c.id = q->r.id;
+            c.tick = s->ticks;
+            c.status = rc;
+            s->done.push_back(c);
+            s->completed += 1;
+            continue;
         }
         if (grow_bytes) {
             if (s->ens_new_bytes) s->arena.release(s->ens_new_off, s->ens_new_bytes);

@@ -139,3 +139,22 @@ def test_served_request_matches_oracle():
     assert got["t"] == 2000.0 and abs(got["steps"] - k) <= 1
     p = assert_parity(got["state"] + (got["t"], 0.0), ref, label="served request")
     _say(p)
+
+
+def test_refused_request_is_reported_and_others_complete():
+    """A request whose inputs are refused when it is started (a NaN in the
+    initial state) completes at once with SWE_E_ARG; the rest of the stream
+    is served as usual."""
+    from paper_1912_02457_amd import Server
+    good = config5_member(80, 60, 0)
+    bad_eta = good.eta.copy()
+    bad_eta[10, 10] = np.nan
+    bad = good.copy(eta=bad_eta)
+    with Server(1 << 28, max_active=4, steps_per_tick=8, device="cuda:0") as srv:
+        srv.submit(good, 200.0, req_id=1)
+        srv.submit(bad, 200.0, req_id=2)
+        srv.submit(good, 100.0, req_id=3)
+        done = {c["id"]: c for c in _drain(srv)}
+    assert done[2]["status"] == -1 and done[2]["steps"] == 0
+    assert done[1]["status"] == 0 and done[1]["t"] == 200.0
+    assert done[3]["status"] == 0 and done[3]["t"] == 100.0

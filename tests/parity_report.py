@@ -6,6 +6,10 @@ test suite).
     python tests/parity_report.py gpu CONFIG DIR      # GPU: own dt, and dt replay
                                                       #      if DIR has the oracle's dts
     python tests/parity_report.py compare CONFIG DIR  # per-field relative L2 / Linf
+    python tests/parity_report.py fp32state CONFIG DIR
+        # the FP64 oracle with its state rounded to float32 after every step,
+        # against DIR/CONFIG_oracle.npz: the deviation that storing the state
+        # in float32 alone produces (a floor for any float32-state solver)
 
 CONFIG is one of config1, config2, config3, config4_m<k> (ensemble member k),
 config5_r<k> (served request k, horizon capped at 2 h).  The oracle writes
@@ -102,7 +106,26 @@ def compare(name, out):
     return res
 
 
+def run_fp32state(name, out):
+    from oracle import oracle as orc
+    from tests._parity import parity
+    wl = workload(name)
+    o = orc.Oracle(wl)
+    st = o.initial_state()
+    t, k = 0.0, 0
+    t0 = time.time()
+    while (t < wl.t_end) if wl.t_end else (k < wl.steps):
+        st, t, _, n = o.run(st, t, nsteps=1, t_end=wl.t_end or 0.0, record_dt=False)
+        st = tuple(np.asarray(a, np.float32).astype(np.float64) for a in st)
+        k += n
+    ref = np.load(os.path.join(out, f"{name}_oracle.npz"))
+    np.savez_compressed(os.path.join(out, f"{name}_fp32state.npz"), eta=st[0], hu=st[1], hv=st[2], t=t)
+    p = parity(st, (ref["eta"], ref["hu"], ref["hv"]), wl.land)
+    print(json.dumps({"config": name, "steps": k, "t": t, "fp32_state_vs_fp64": {a: float(b) for a, b in p.items()},
+                      "seconds": time.time() - t0}), flush=True)
+
+
 if __name__ == "__main__":
     mode, name, out = sys.argv[1], sys.argv[2], sys.argv[3]
     os.makedirs(out, exist_ok=True)
-    {"oracle": run_oracle, "gpu": run_gpu, "compare": compare}[mode](name, out)
+    {"oracle": run_oracle, "gpu": run_gpu, "compare": compare, "fp32state": run_fp32state}[mode](name, out)

@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--serve-max-active", type=int, default=64)
     ap.add_argument("--serve-steps-per-tick", type=int, default=24)
     ap.add_argument("--serve-rows", type=int, default=0, help="rows per tile of the server's ensemble (0 = default)")
+    ap.add_argument("--serve-baseline-requests", type=int, default=60,
+                    help="requests of the stream run one by one for the unbatched comparison")
     ap.add_argument("--serve-time-scale", type=float, default=0.1,
                     help="factor on horizons and inter-arrival times of the request stream")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -398,7 +400,29 @@ def bench_serving(a, torch):
         "rows_per_wave": a.serve_rows,
         "arena_peak_GiB": st["arena_peak"] / 2**30,
         "host_s": {k[5:-2]: round(st[k], 3) for k in st if k.startswith("host_")},
+        "one_by_one": serve_one_by_one(reqs[:a.serve_baseline_requests], horizons, torch),
     }
+
+
+def serve_one_by_one(reqs, horizons, torch):
+    """The plain alternative to batching: the same requests run one after the
+    other, each alone on the GPU (its own domain, run_until its horizon).
+    Inputs are built before the clock starts; cell-updates/s over the run."""
+    from paper_1912_02457_amd import Domain
+    from workloads.configs import config5_member
+    wls = [config5_member(r["nx"], r["ny"], 0.0) for r in reqs]
+    cells = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for wl, h in zip(wls, horizons):
+        d = Domain.from_workload(wl, device="cuda:0")
+        k = d.run_until(h)
+        cells += wl.nx * wl.ny * k
+        d.close()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"requests": len(wls), "value": cells / el, "unit": "cell-updates/s",
+            "note": "first requests of the same stream, each run alone in arrival order (init and run_until)"}
 
 
 def _progress(msg):

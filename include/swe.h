@@ -331,6 +331,72 @@ int swe_server_get_stats(swe_server *s, swe_server_stats *st);
 /* Drops every active and waiting request and frees the server. */
 void swe_server_destroy(swe_server *s);
 
+/* ---- preprocessing of the input fields ----------------------------------
+ * Init-time steps that turn model data into the inputs of swe_init_domain,
+ * run on the device.  Every array pointer is a DEVICE pointer to a dense
+ * row-major array (row pitch = width, x fastest); outputs must not overlap
+ * inputs; planes of refined outputs must be 8-byte aligned.  The calls only
+ * enqueue kernels on hip_stream (a hipStream_t, may be NULL) and return;
+ * launch failures give SWE_E_HIP.  Non-finite input values propagate to the
+ * output; they are not detected.  No device memory is allocated. */
+
+/* Corner depths from cell-centre depths (section "Bathymetry"): the initial
+ * guess of eqs. recon_1-3 -- a minmod-limited plane per cell (a difference
+ * toward land or outside the domain counts as 0), evaluated at the cell's
+ * corners and averaged over the water cells meeting at each corner -- then
+ * `iters` rounds of: misfit Hm - (mean of the cell's four corners) on water
+ * cells, its corner estimate by the same equations ADDED to the corners,
+ * and smoothing H <- (1 - smooth) H + (smooth/4) (sum of the 4 neighbours),
+ * a neighbour outside the domain replaced by the corner itself (smooth =
+ * 0.5 gives H/2 + sum/8).  Corners touching no water cell hold the mean of
+ * the four cell values around them (edge cells repeated).
+ *   Hm [ny][nx] metres, positive down; land [ny][nx] (nonzero = land) or NULL;
+ *   Hc [ny+1][nx+1] output; scratch [ny+1][nx+1] floats, required when
+ *   iters > 0 (contents overwritten).  nx, ny >= 1; iters in [0, 100000];
+ *   smooth in [0, 1].
+ * Errors: SWE_E_ARG (sizes, NULL pointers, a corner plane of 4 GiB or more,
+ * parameters out of range), SWE_E_HIP. */
+int swe_reconstruct_bathymetry(int32_t nx, int32_t ny, const float *Hm, const uint8_t *land, int32_t iters,
+                               float smooth, float *Hc, float *scratch, void *hip_stream);
+
+/* One erosion of the land mask (section "Bathymetry", Figure erode_land):
+ * a land cell with a water 4-neighbour (cells outside the domain count as
+ * land) becomes water of depth land_depth, its eta the largest eta among
+ * those water neighbours (gray dilation), its momenta 0; every other cell is
+ * copied.  land_out holds 0/1.  eta, hu, hv may each be NULL (with their
+ * outputs NULL).  Repeat the call to erode further.
+ * Errors: SWE_E_ARG (sizes, missing land/Hm/outputs, mismatched optional
+ * pairs, non-finite land_depth), SWE_E_HIP. */
+int swe_erode_land(int32_t nx, int32_t ny, const uint8_t *land, const float *Hm, const float *eta,
+                   const float *hu, const float *hv, float land_depth, uint8_t *land_out, float *Hm_out,
+                   float *eta_out, float *hu_out, float *hv_out, void *hip_stream);
+
+/* Factor-two refinement (section "Refinement and coarsening of grid"):
+ *   fields: n_fields planes [n_fields][ny][nx] -> fields_out
+ *     [n_fields][2ny][2nx]; each cell's linear reconstruction with slopes
+ *     minmod(theta D-, (D- + D+)/2, theta D+) (a difference toward land or
+ *     outside the domain is 0; land cells stay constant) evaluated at the
+ *     four sub-cell centres, which preserves the cell average;
+ *   land -> land_out [2ny][2nx] (children inherit; needs n_fields >= 1;
+ *     land may be NULL = all water, land_out may be NULL);
+ *   Hc [ny+1][nx+1] -> Hc_out [2ny+1][2nx+1]: the bilinear surface at the
+ *     refined intersections (both NULL to skip).
+ * theta in [1, 2] (1 = plain minmod).
+ * Errors: SWE_E_ARG (sizes, pointers, theta, a refined corner plane of
+ * 4 GiB or more), SWE_E_HIP. */
+int swe_refine2(int32_t nx, int32_t ny, int32_t n_fields, const float *fields, const uint8_t *land, float theta,
+                float *fields_out, uint8_t *land_out, const float *Hc, float *Hc_out, void *hip_stream);
+
+/* Factor-two coarsening (same section) of a grid with even nx, ny >= 2:
+ * a coarse cell is the average of its water children (of all four when all
+ * are land) and is land when all four children are; corner depths are
+ * sampled at the coarse intersections.  Shapes: fields [n_fields][ny][nx]
+ * -> [n_fields][ny/2][nx/2]; land -> [ny/2][nx/2] (land_out needs land and
+ * n_fields >= 1); Hc [ny+1][nx+1] -> [ny/2+1][nx/2+1].
+ * Errors: SWE_E_ARG (odd or small sizes, pointers), SWE_E_HIP. */
+int swe_coarsen2(int32_t nx, int32_t ny, int32_t n_fields, const float *fields, const uint8_t *land,
+                 float *fields_out, uint8_t *land_out, const float *Hc, float *Hc_out, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

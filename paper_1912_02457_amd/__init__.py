@@ -9,6 +9,6 @@ raises ImportError, there is no CPU fallback.
 
 from .swe import (  # noqa: F401
     BC_NESTED, BC_PERIODIC, BC_WALL, FRICTION_LINEAR, FRICTION_MANNING, FRICTION_NONE,
-    FRICTION_QUADRATIC, LIB_PATH, Domain, Ensemble, Params, Server, SweError, load_library, make_params,
-    workspace_bytes,
+    FRICTION_QUADRATIC, LIB_PATH, Domain, Ensemble, Params, Server, SweError, coarsen2, erode_land,
+    load_library, make_params, reconstruct_bathymetry, refine2, workspace_bytes,
 )

@@ -4,7 +4,8 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["csrc/swe_kernels.hip", "csrc/swe_api.hip", "csrc/swe_ensemble.hip", "csrc/swe_server.hip"]
+SOURCES = ["csrc/swe_kernels.hip", "csrc/swe_api.hip", "csrc/swe_ensemble.hip", "csrc/swe_server.hip",
+           "csrc/swe_preprocess.hip"]
 LIB = os.path.join(HERE, "lib", "libswe_hip.so")
 ARCH = os.environ.get("SWE_OFFLOAD_ARCH", "gfx950")
 

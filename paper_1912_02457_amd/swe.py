@@ -107,6 +107,12 @@ SIGNATURES = {
     "swe_server_poll": (C.c_int, [_VP, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     "swe_server_get_stats": (C.c_int, [_VP, C.c_void_p]),
     "swe_server_destroy": (None, [_VP]),
+    "swe_reconstruct_bathymetry": (C.c_int, [C.c_int32, C.c_int32, _VP, _VP, C.c_int32, C.c_float, _VP, _VP,
+                                             _VP]),
+    "swe_erode_land": (C.c_int, [C.c_int32, C.c_int32, _VP, _VP, _VP, _VP, _VP, C.c_float, _VP, _VP, _VP, _VP,
+                                 _VP, _VP]),
+    "swe_refine2": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _VP, _VP, C.c_float, _VP, _VP, _VP, _VP, _VP]),
+    "swe_coarsen2": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
 }
 
 _lib = None
@@ -495,3 +501,112 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ---- preprocessing of the input fields (device tensors in and out) --------
+
+def _dev(t, dtype, shape, name):
+    """Device pointer of a contiguous CUDA tensor of the given dtype/shape."""
+    import torch
+    if t is None:
+        return None
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_of(t, stream):
+    import torch
+    return C.c_void_p((stream if stream is not None else torch.cuda.current_stream(t.device)).cuda_stream)
+
+
+def reconstruct_bathymetry(Hm, land=None, *, iters: int = 10, smooth: float = 0.5, out=None, scratch=None,
+                           stream=None):
+    """Corner depths [ny+1, nx+1] from cell depths Hm [ny, nx] on the device
+    (``swe_reconstruct_bathymetry``); returns ``out``."""
+    import torch
+    ny, nx = Hm.shape
+    if out is None:
+        out = torch.empty((ny + 1, nx + 1), dtype=torch.float32, device=Hm.device)
+    if scratch is None and iters > 0:
+        scratch = torch.empty((ny + 1, nx + 1), dtype=torch.float32, device=Hm.device)
+    load_library()
+    _check(_lib.swe_reconstruct_bathymetry(nx, ny, _dev(Hm, torch.float32, (ny, nx), "Hm"),
+                                           _dev(land, torch.uint8, (ny, nx), "land"), int(iters), float(smooth),
+                                           _dev(out, torch.float32, (ny + 1, nx + 1), "out"),
+                                           _dev(scratch, torch.float32, (ny + 1, nx + 1), "scratch"),
+                                           _stream_of(Hm, stream)))
+    return out
+
+
+def erode_land(land, Hm, eta=None, hu=None, hv=None, *, land_depth: float = 5.0, stream=None):
+    """One erosion of the land mask on the device (``swe_erode_land``).
+    Returns (land, Hm, eta, hu, hv) as new tensors (None where not given)."""
+    import torch
+    ny, nx = land.shape
+    outs = [torch.empty_like(land), torch.empty_like(Hm)] + [None if a is None else torch.empty_like(a)
+                                                             for a in (eta, hu, hv)]
+    f32 = torch.float32
+    load_library()
+    _check(_lib.swe_erode_land(nx, ny, _dev(land, torch.uint8, (ny, nx), "land"), _dev(Hm, f32, (ny, nx), "Hm"),
+                               _dev(eta, f32, (ny, nx), "eta"), _dev(hu, f32, (ny, nx), "hu"),
+                               _dev(hv, f32, (ny, nx), "hv"), float(land_depth),
+                               *[_dev(o, torch.uint8 if k == 0 else f32, (ny, nx), "out")
+                                 for k, o in enumerate(outs)], _stream_of(land, stream)))
+    return tuple(outs)
+
+
+def refine2(fields=None, land=None, Hc=None, *, theta: float = 1.0, stream=None):
+    """Factor-two refinement on the device (``swe_refine2``).  fields is a
+    [n, ny, nx] float32 tensor (or None); returns (fields, land, Hc) refined
+    (None where not given)."""
+    import torch
+    ref = next(t for t in (fields, land, Hc) if t is not None)
+    if fields is not None:
+        nf, ny, nx = fields.shape
+    elif land is not None:
+        (ny, nx), nf = land.shape, 0
+    else:
+        ny, nx, nf = Hc.shape[0] - 1, Hc.shape[1] - 1, 0
+    if land is not None and nf == 0:
+        raise ValueError("refining the land mask needs at least one field")
+    dev = ref.device
+    fo = None if fields is None else torch.empty((nf, 2 * ny, 2 * nx), dtype=torch.float32, device=dev)
+    lo = None if land is None else torch.empty((2 * ny, 2 * nx), dtype=torch.uint8, device=dev)
+    ho = None if Hc is None else torch.empty((2 * ny + 1, 2 * nx + 1), dtype=torch.float32, device=dev)
+    load_library()
+    _check(_lib.swe_refine2(nx, ny, nf, _dev(fields, torch.float32, (nf, ny, nx), "fields"),
+                            _dev(land, torch.uint8, (ny, nx), "land"), float(theta), _dev(fo, torch.float32,
+                            (nf, 2 * ny, 2 * nx), "fields_out"), _dev(lo, torch.uint8, (2 * ny, 2 * nx), "land_out"),
+                            _dev(Hc, torch.float32, (ny + 1, nx + 1), "Hc"),
+                            _dev(ho, torch.float32, (2 * ny + 1, 2 * nx + 1), "Hc_out"), _stream_of(ref, stream)))
+    return fo, lo, ho
+
+
+def coarsen2(fields=None, land=None, Hc=None, *, stream=None):
+    """Factor-two coarsening on the device (``swe_coarsen2``); nx, ny even.
+    Returns (fields, land, Hc) coarsened (None where not given)."""
+    import torch
+    ref = next(t for t in (fields, land, Hc) if t is not None)
+    if fields is not None:
+        nf, ny, nx = fields.shape
+    elif land is not None:
+        (ny, nx), nf = land.shape, 0
+    else:
+        ny, nx, nf = Hc.shape[0] - 1, Hc.shape[1] - 1, 0
+    if land is not None and nf == 0:
+        raise ValueError("coarsening the land mask needs at least one field")
+    dev = ref.device
+    cy, cx = ny // 2, nx // 2
+    fo = None if fields is None else torch.empty((nf, cy, cx), dtype=torch.float32, device=dev)
+    lo = None if land is None else torch.empty((cy, cx), dtype=torch.uint8, device=dev)
+    ho = None if Hc is None else torch.empty((cy + 1, cx + 1), dtype=torch.float32, device=dev)
+    load_library()
+    _check(_lib.swe_coarsen2(nx, ny, nf, _dev(fields, torch.float32, (nf, ny, nx), "fields"),
+                             _dev(land, torch.uint8, (ny, nx), "land"), _dev(fo, torch.float32, (nf, cy, cx),
+                             "fields_out"), _dev(lo, torch.uint8, (cy, cx), "land_out"),
+                             _dev(Hc, torch.float32, (ny + 1, nx + 1), "Hc"),
+                             _dev(ho, torch.float32, (cy + 1, cx + 1), "Hc_out"), _stream_of(ref, stream)))
+    return fo, lo, ho

@@ -187,3 +187,39 @@ def test_product_path_has_no_oracle_or_cpu_fallback():
             if fn.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "oracle" not in txt.lower().replace("oracle_", ""), fn
+
+
+def test_preprocess_rejects_invalid_arguments(lib):
+    """The preprocessing entry points refuse bad sizes, pointers and
+    parameters before enqueueing anything (the pointers here are never
+    dereferenced: each call fails its argument checks first)."""
+    from paper_1912_02457_amd import swe
+    p = C.c_void_p(0x1000)  # never dereferenced
+    E = swe.SWE_E_ARG
+    rb = lib.swe_reconstruct_bathymetry
+    assert rb(0, 5, p, None, 0, 0.5, p, p, None) == E
+    assert rb(5, 5, None, None, 0, 0.5, p, p, None) == E
+    assert rb(5, 5, p, None, 0, 0.5, None, p, None) == E
+    assert rb(5, 5, p, None, 3, 0.5, p, None, None) == E      # scratch needed
+    assert rb(5, 5, p, None, -1, 0.5, p, p, None) == E
+    assert rb(5, 5, p, None, 2, 1.5, p, p, None) == E
+    assert rb(5, 5, p, None, 2, float("nan"), p, p, None) == E
+    assert b"smooth" in lib.swe_last_error()
+    assert rb(40000, 40000, p, None, 2, 0.5, p, p, None) == E  # 6.4 GB corner plane
+    el = lib.swe_erode_land
+    assert el(0, 4, p, p, None, None, None, 5.0, p, p, None, None, None, None) == E
+    assert el(4, 4, None, p, None, None, None, 5.0, p, p, None, None, None, None) == E
+    assert el(4, 4, p, p, p, None, None, 5.0, p, p, None, None, None, None) == E   # eta without output
+    assert el(4, 4, p, p, None, None, None, float("inf"), p, p, None, None, None, None) == E
+    rf = lib.swe_refine2
+    assert rf(4, 4, 1, p, None, 0.5, p, None, None, None, None) == E     # theta < 1
+    assert rf(4, 4, 1, None, None, 1.0, p, None, None, None, None) == E
+    assert rf(4, 4, 0, None, p, 1.0, None, p, None, None, None) == E     # land_out with no field
+    assert rf(4, 4, 1, p, None, 1.0, p, p, None, None, None) == E        # land_out without land
+    assert rf(4, 4, 0, None, None, 1.0, None, None, p, None, None) == E  # Hc without Hc_out
+    assert rf(30000, 30000, 0, None, None, 1.0, None, None, p, p, None) == E
+    cs = lib.swe_coarsen2
+    assert cs(5, 4, 1, p, None, p, None, None, None, None) == E          # odd nx
+    assert cs(4, 0, 1, p, None, p, None, None, None, None) == E
+    assert cs(4, 4, 1, p, None, p, p, None, None, None) == E             # land_out without land
+    assert cs(4, 4, 0, None, None, None, None, p, None, None) == E

@@ -3,6 +3,11 @@
 This package only builds inputs (grids, bathymetry, Coriolis fields, initial
 states, forcing snapshots).  It holds none of the finite-volume scheme's
 arithmetic, so both implementations can consume the very same FP32 arrays.
+The coastal generator builds its corner depths with a vectorised numpy
+version of the bathymetry reconstruction of section "Bathymetry": part of
+the input recipe, imported by neither the oracle nor the HIP library (the
+device preprocessing is checked against the oracle on the raw cell depths
+that ``coastal_cells`` returns).
 """
 
 from .configs import (  # noqa: F401
@@ -15,6 +20,7 @@ from .configs import (  # noqa: F401
     FRIC_QUADRATIC,
     Workload,
     add_wind_field,
+    coastal_cells,
     config1,
     config2,
     config3,

@@ -216,14 +216,23 @@ def config1() -> Workload:
     )
 
 
-def _coastal(nx, ny, dx, seed_bathy, seed_land, land_frac=0.35, recon_iters=10):
+def coastal_cells(nx, ny, seed_bathy, seed_land, land_frac=0.35):
+    """Cell-centre depths and land mask of the coastal generator, before the
+    corners are built: log-normal depths (median 150 m, 5..3000 m) from
+    Gaussian-smoothed noise (sigma 8 cells), land where an independent smooth
+    field (sigma 16 cells) is below its land_frac quantile, land cells at
+    -5 m (above the datum).  Returns (Hm float64 [ny][nx], land bool)."""
     rng = np.random.default_rng(seed_bathy)
     Z = _smooth_noise(rng, (ny, nx), 8.0)
     Hm = np.clip(150.0 * np.exp(1.0 * Z), 5.0, 3000.0)
     rng2 = np.random.default_rng(seed_land)
     L = _smooth_noise(rng2, (ny, nx), 16.0)
     land = L < np.percentile(L, 100.0 * land_frac)
-    Hm = np.where(land, -5.0, Hm)
+    return np.where(land, -5.0, Hm), land
+
+
+def _coastal(nx, ny, dx, seed_bathy, seed_land, land_frac=0.35, recon_iters=10):
+    Hm, land = coastal_cells(nx, ny, seed_bathy, seed_land, land_frac)
     wet = ~land
     Hc, cnt = reconstruct_corners(Hm, wet, iters=recon_iters, land_value=-5.0)
     # every intersection touching a wet cell stays at least 1 m deep

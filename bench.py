@@ -11,7 +11,9 @@ the headline figure it carries
               the persistent ensemble launch, against a per-domain loop;
   "serving":  the continuous-batching server on Poisson arrivals of forecast
               requests (time-scaled: horizons and inter-arrival times x0.1),
-              with p50/p99 latency next to throughput.
+              with p50/p99 latency next to throughput;
+  "preprocess": the device preprocessing of the same grid's cell depths
+              (bathymetry reconstruction, land erosion, refinement).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                     [--no-ensemble] [--no-serving]
@@ -72,6 +74,10 @@ def parse():
                     help="factor on horizons and inter-arrival times of the request stream")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run warmup + this many steps (for rocprofv3 runs), no JSON")
+    ap.add_argument("--no-preprocess", action="store_true")
+    ap.add_argument("--preprocess-only", action="store_true",
+                    help="only the device preprocessing section (for profiler runs)")
+    ap.add_argument("--preprocess-reps", type=int, default=50)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="with --profile-steps: also run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -425,6 +431,134 @@ def serve_one_by_one(reqs, horizons, torch):
             "note": "first requests of the same stream, each run alone in arrival order (init and run_until)"}
 
 
+PRE_SOURCE = os.path.join(ROOT, "paper_1912_02457_amd", "csrc", "swe_preprocess.hip")
+PRE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_recon_round_kernel_norkyst_2600x900.md")
+
+
+def measured_pre_traffic():
+    """HBM bytes per launch of the reconstruction round kernel from the
+    committed FETCH_SIZE / WRITE_SIZE runs, or None if the source changed."""
+    if not os.path.exists(PRE_TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(PRE_TRAFFIC_FILE):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha1") != hashlib.sha1(open(PRE_SOURCE, "rb").read()).hexdigest():
+        return None
+    v = vals.get("recon_round_hbm_bytes_per_launch")
+    return None if v is None else float(v)
+
+
+def bench_preprocess(a, np, torch):
+    """Device preprocessing of the 2600 x 900 coastal grid (the cell depths
+    and land mask behind the headline domain): bathymetry reconstruction
+    (10 rounds), one land erosion, factor-two refinement of (eta, hu, hv),
+    land and corners.  Each operation is captured once in a HIP graph and
+    replayed; HIP events on the replay stream time the replays.  The round
+    kernel's average duration = (time of 10-round calls - time of 0-round
+    calls) / 10."""
+    from paper_1912_02457_amd import swe
+    from workloads import coastal_cells
+
+    nx, ny = 2600, 900
+    Hm_np, land_np = coastal_cells(nx, ny, 2, 3)
+    dev = torch.device("cuda:0")
+    Hm = torch.from_numpy(Hm_np.astype(np.float32)).to(dev)
+    land = torch.from_numpy(land_np.astype(np.uint8)).to(dev)
+    state = torch.zeros((3, ny, nx), dtype=torch.float32, device=dev)
+    Hc = torch.empty((ny + 1, nx + 1), dtype=torch.float32, device=dev)
+    scratch = torch.empty_like(Hc)
+    side = torch.cuda.Stream(dev)
+
+    ops = {
+        "recon10": lambda: swe.reconstruct_bathymetry(Hm, land, iters=10, out=Hc, scratch=scratch),
+        "recon0": lambda: swe.reconstruct_bathymetry(Hm, land, iters=0, out=Hc, scratch=scratch),
+        "erode": lambda: swe.erode_land(land, Hm, state[0], state[1], state[2]),
+        "refine": lambda: swe.refine2(state, land, Hc),
+    }
+    if a.preprocess_only and a.copy_calibration:
+        x = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+    reps = a.preprocess_reps
+    ms = {}
+    for name, fn in ops.items():
+        with torch.cuda.stream(side):
+            for _ in range(3):
+                fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            fn()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            g.replay()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(side)
+            for _ in range(reps):
+                g.replay()
+            e1.record(side)
+        torch.cuda.synchronize()
+        ms[name] = e0.elapsed_time(e1) / reps
+        del g
+    # the same round kernel on an 8192 x 8192 grid (a smooth analytic
+    # bottom with a land band; timing only), where the launch holds about
+    # four times as many waves as are resident at once
+    L_ = 8192
+    yy, xx = torch.meshgrid(torch.arange(L_, device=dev, dtype=torch.float32),
+                            torch.arange(L_, device=dev, dtype=torch.float32), indexing="ij")
+    Hm_l = 200.0 + 150.0 * torch.sin(xx / 97.0) * torch.cos(yy / 131.0)
+    land_l = ((torch.sin(xx / 611.0) + torch.cos(yy / 389.0)) > 1.2).to(torch.uint8)
+    Hm_l = torch.where(land_l > 0, torch.full_like(Hm_l, -5.0), Hm_l).contiguous()
+    del yy, xx
+    Hc_l = torch.empty((L_ + 1, L_ + 1), dtype=torch.float32, device=dev)
+    scratch_l = torch.empty_like(Hc_l)
+    for name, it in (("large10", 10), ("large0", 0)):
+        fn = (lambda it=it: swe.reconstruct_bathymetry(Hm_l, land_l, iters=it, out=Hc_l, scratch=scratch_l))
+        with torch.cuda.stream(side):
+            fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(side)
+            for _ in range(5):
+                fn()
+            e1.record(side)
+        torch.cuda.synchronize()
+        ms[name] = e0.elapsed_time(e1) / 5
+    del Hm_l, land_l, Hc_l, scratch_l
+    CL, NL = (L_ + 1) ** 2, L_ * L_
+    large_round_ms = (ms["large10"] - ms["large0"]) / 10.0
+    large_gbs = (8 * CL + 5 * NL) / (large_round_ms * 1e-3) / 1e9
+
+    C_, N_ = (ny + 1) * (nx + 1), nx * ny
+    round_ms = (ms["recon10"] - ms["recon0"]) / 10.0
+    round_bytes = 8 * C_ + 5 * N_          # corners in and out, cell depths, land flags
+    gbs = round_bytes / (round_ms * 1e-3) / 1e9
+    traffic = measured_pre_traffic()
+    erode_bytes = 34 * N_
+    refine_bytes = 13 * N_ + 4 * C_ + 52 * N_ + 4 * (2 * ny + 1) * (2 * nx + 1)
+    return {
+        "workload": "norkyst_2600x900 coastal cell depths + land (seeds 2, 3)",
+        "reconstruct": {"ms_per_call": ms["recon10"], "rounds": 10, "init_ms": ms["recon0"],
+                        "corner_rounds_per_s": C_ * 11 / (ms["recon10"] * 1e-3),
+                        "roofline": {"bound": "hbm", "kernel": "recon_round_kernel<false>", "achieved": gbs,
+                                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                                     "traffic": traffic, "avg_launch_ms": round_ms,
+                                     "algorithmic_bytes_per_launch": round_bytes}},
+        "reconstruct_8192x8192": {"ms_per_call": ms["large10"], "avg_round_ms": large_round_ms,
+                                  "GBs": large_gbs, "frac": large_gbs / HBM_PEAK_GBS,
+                                  "timing": "5 eager calls between HIP events"},
+        "erode": {"ms_per_call": ms["erode"], "GBs": erode_bytes / (ms["erode"] * 1e-3) / 1e9},
+        "refine": {"ms_per_call": ms["refine"], "fields": 3,
+                   "GBs": refine_bytes / (ms["refine"] * 1e-3) / 1e9},
+        "timing": f"HIP graph of each call replayed {reps}x between HIP events on the replay stream",
+    }
+
+
 def _progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -440,6 +574,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if a.preprocess_only:
+        print(json.dumps({"preprocess": bench_preprocess(a, np, torch)}), flush=True)
+        return
     out, wl = bench_single(a, np, torch)
     if out is None:
         return
@@ -450,6 +587,9 @@ def main():
     if not a.no_serving:
         out["serving"] = bench_serving(a, torch)
         _progress(f"serving: p50 {out['serving']['latency_s']['p50']:.3f} s")
+    if not a.no_preprocess:
+        out["preprocess"] = bench_preprocess(a, np, torch)
+        _progress(f"preprocess: reconstruction {out['preprocess']['reconstruct']['ms_per_call']:.3f} ms")
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds)
         _progress("cpu baseline done")

@@ -5,6 +5,7 @@
 // (section "Refinement and coarsening of grid").  Device pointers in and out,
 // asynchronous on the caller's stream, no device memory of the library's own.
 #include <cmath>
+#include <algorithm>
 #include <cstdint>
 #include <string>
 
@@ -15,9 +16,7 @@ namespace {
 using swe::set_error;
 
 // ---------------------------------------------------------------------------
-// Bathymetry reconstruction.  One launch per round; each 256-thread block
-// produces a 64 x 16 tile of corners from an LDS window of the previous
-// round's corners (3-corner halo), the cell values and the water flags.
+// Bathymetry reconstruction, one launch per round.
 //   round 0 (INIT): corners = the average over the water cells meeting there
 //     of each cell's limited plane evaluated at the corner (eqs. recon_1-3)
 //     applied to the cell values themselves;
@@ -27,128 +26,155 @@ using swe::set_error;
 //     neighbour outside the domain replaced by the corner itself.
 // Corners that touch no water cell hold the mean of the four cell values
 // around them (edge cells repeated).
-constexpr int RTX = 64, RTY = 16, RTHREADS = 256;
-constexpr int WCR = RTY + 6, WCC = RTX + 6;  // corner window
-constexpr int WMR = RTY + 5, WMC = RTX + 5;  // cell window
+//
+// Work decomposition: one wave per (strip, row segment).  Lane l holds
+// corner column I = 58 s - 3 + l and cell column i = I (the cell to the
+// upper right of the corner); an output corner reads columns I-3 .. I+3, so
+// lanes 3..60 store and the six others are halo.  The wave walks up the
+// rows with a register pipeline: the step that loads corner row a and cell
+// row a-1 computes the misfit of cell row a-1, the slopes and corner
+// contributions of cell row a-2, the corrected corners of row a-2 and the
+// smoothed output row a-3.  Neighbouring columns come through DPP lane
+// shifts; the next row's loads are issued before the current row is used.
+constexpr int RSTRIP = 58;
+
+constexpr int kDppShl1 = 0x130;  // wave_shl:1 -- value of lane + 1
+constexpr int kDppShr1 = 0x138;  // wave_shr:1 -- value of lane - 1
+__device__ __forceinline__ int lane_right(int v) { return __builtin_amdgcn_update_dpp(0, v, kDppShl1, 0xF, 0xF, false); }
+__device__ __forceinline__ int lane_left(int v) { return __builtin_amdgcn_update_dpp(0, v, kDppShr1, 0xF, 0xF, false); }
+__device__ __forceinline__ float lane_right(float v) { return __int_as_float(lane_right(__float_as_int(v))); }
+__device__ __forceinline__ float lane_left(float v) { return __int_as_float(lane_left(__float_as_int(v))); }
+
+// Element access through a 32-bit byte offset from a uniform base pointer
+// (the scalar-base + vector-offset addressing form; no 64-bit address
+// arithmetic per lane).  Every plane stays below 4 GiB.
+__device__ __forceinline__ float ldf(const float *__restrict__ base, uint32_t i)
+{
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + (i << 2));
+}
+__device__ __forceinline__ int ldb(const uint8_t *__restrict__ base, uint32_t i)
+{
+    return *reinterpret_cast<const uint8_t *>(reinterpret_cast<const char *>(base) + i);
+}
+__device__ __forceinline__ void stf(float *__restrict__ base, uint32_t i, float v)
+{
+    *reinterpret_cast<float *>(reinterpret_cast<char *>(base) + (i << 2)) = v;
+}
 
 __device__ __forceinline__ float minmod2(float a, float b)
 {
-    if (a > 0.0f && b > 0.0f) return fminf(a, b);
-    if (a < 0.0f && b < 0.0f) return fmaxf(a, b);
-    return 0.0f;
+    const float mn = fminf(a, b), mx = fmaxf(a, b);
+    return ((a > 0.0f) & (b > 0.0f)) ? mn : (((a < 0.0f) & (b < 0.0f)) ? mx : 0.0f);
 }
 
 // Blocks go to the 8 XCDs round-robin; give each XCD a contiguous run of
-// tiles so that neighbouring tiles share halo lines in the same L2.
-__device__ __forceinline__ int xcd_tile(int b, int n)
+// blocks so that neighbouring strips and segments share lines in one L2.
+__device__ __forceinline__ int xcd_block(int b, int n)
 {
     int q = n >> 3, r = n & 7, x = b & 7, k = b >> 3;
     return x * q + min(x, r) + k;
 }
 
-template <bool INIT>
-__global__ __launch_bounds__(RTHREADS) void recon_round_kernel(int nx, int ny, int nbx, const float *__restrict__ Hm,
-                                                               const uint8_t *__restrict__ land,
-                                                               const float *__restrict__ Hin, float w,
-                                                               float *__restrict__ Hout)
+template <bool INIT, int R>
+__global__ __launch_bounds__(256) void recon_round_kernel(int nx, int ny, int nsx, int nitems,
+                                                          const float *__restrict__ Hm,
+                                                          const uint8_t *__restrict__ land,
+                                                          const float *__restrict__ Hin, float w,
+                                                          float *__restrict__ Hout)
 {
-    __shared__ float sH[WCR][WCC];  // corners in, then corrected corners
-    __shared__ float sM[WMR][WMC];  // cell values
-    __shared__ float sD[WMR][WMC];  // misfit (or cell values in round 0)
-    __shared__ float sSx[WMR][WMC], sSy[WMR][WMC];
-    __shared__ uint8_t sW[WMR][WMC];  // water cell inside the domain
+    constexpr int NS = R + 6;  // steps: three warm-up rows below, three above
+    const int lane = threadIdx.x & 63;
+    const int item = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (item >= nitems) return;  // whole waves leave together
+    const int J0 = (item / nsx) * R, I = (item % nsx) * RSTRIP - 3 + lane;
+    const uint32_t Ic = (uint32_t)min(max(I, 0), nx), ic = (uint32_t)min(max(I, 0), nx - 1);
+    const bool col_in = I >= 0 && I < nx;
+    const bool store = lane >= 3 && lane < 3 + RSTRIP && I <= nx;
+    const uint32_t nxc = (uint32_t)nx + 1;
+    const float wq = 0.25f * w, wp = 1.0f - w;
+    const int a0 = J0 - 3;
 
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int J0 = (t / nbx) * RTY, I0 = (t % nbx) * RTX;
-    const int nxc = nx + 1;
-    const int tid = threadIdx.x;
+    // every load of the segment first (clamped rows: always valid
+    // addresses), so the wave waits for memory once, not once per row
+    float Hb[NS], Mb[NS];
+    int Lb[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        Hb[k] = INIT ? 0.f : ldf(Hin, (uint32_t)min(max(a0 + k, 0), ny) * nxc + Ic);
+        Mb[k] = ldf(Hm, (uint32_t)min(max(a0 + k - 1, 0), ny - 1) * (uint32_t)nx + ic);
+        Lb[k] = 0;
+    }
+    if (land) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) Lb[k] = ldb(land, (uint32_t)min(max(a0 + k - 1, 0), ny - 1) * (uint32_t)nx + ic);
+    }
 
-    if (!INIT) {
-        for (int idx = tid; idx < WCR * WCC; idx += RTHREADS) {
-            int r = idx / WCC, c = idx - r * WCC;
-            int J = J0 - 3 + r, I = I0 - 3 + c;
-            bool in = J >= 0 && J <= ny && I >= 0 && I <= nx;
-            sH[r][c] = in ? Hin[(uint32_t)J * (uint32_t)nxc + (uint32_t)I] : 0.0f;
+    // pipeline registers; names give the row relative to the newest corner row a
+    float H1 = 0.f, H1r = 0.f, H2 = 0.f;       // corners a-1 (and its right neighbour), a-2
+    float D2 = 0.f, D3 = 0.f;                  // misfit of cell rows a-2, a-3
+    int W2 = 0, W3 = 0, W4 = 0, W3l = 0, W4l = 0;  // water flags (l: of the cell to the left)
+    float UR3 = 0.f, UL3 = 0.f;                // cell row a-3: estimates at its upper corners
+    float P3 = 0.f, P4 = 0.f;                  // corrected corners of rows a-3, a-4
+    float M1 = 0.f, M2 = 0.f, M3 = 0.f;        // clamped cell values, rows a-2, a-3, a-4
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int a = a0 + k;
+        const float Ha = Hb[k], Mc = Mb[k];
+
+        // misfit of cell row a-1
+        const int W1 = ((a - 1 >= 0) & (a - 1 < ny) & col_in & (Lb[k] == 0)) ? 1 : 0;
+        const float Har = lane_right(Ha);
+        const float D1 = W1 ? (INIT ? Mc : Mc - 0.25f * (H1 + H1r + Ha + Har)) : 0.f;
+
+        // slopes and corner estimates of cell row a-2
+        const float Dl = lane_left(D2), Dr = lane_right(D2);
+        const int W2l = lane_left(W2), W2r = lane_right(W2);
+        const float sx = minmod2(W2l ? D2 - Dl : 0.f, W2r ? Dr - D2 : 0.f);
+        const float sy = minmod2(W3 ? D2 - D3 : 0.f, W1 ? D1 - D2 : 0.f);
+        const float UR2 = D2 + 0.5f * sx + 0.5f * sy, UL2 = D2 - 0.5f * sx + 0.5f * sy;
+        const float DR2 = D2 + 0.5f * sx - 0.5f * sy, DL2 = D2 - 0.5f * sx - 0.5f * sy;
+
+        // corrected corner row a-2: cells (a-3, I-1), (a-3, I), (a-2, I-1), (a-2, I)
+        const float UR3l = lane_left(UR3), DR2l = lane_left(DR2);
+        // absent cells add +0, which leaves the running sum unchanged;
+        // dividing by 1, 2 or 4 is exact, by 3 within one rounding
+        const float acc = (((W3l ? UR3l : 0.f) + (W3 ? UL3 : 0.f)) + (W2l ? DR2l : 0.f)) + (W2 ? DL2 : 0.f);
+        const int cnt = W3l + W3 + W2l + W2;
+        const float est = acc * (cnt == 4 ? 0.25f : cnt == 3 ? 1.0f / 3.0f : cnt == 2 ? 0.5f : 1.0f);
+        const float P2 = INIT ? est : H2 + est;
+
+        // output row Y = a-3 (the first six steps only fill the pipeline)
+        const int Y = a - 3;
+        if (k >= 6) {
+            const float P3l = lane_left(P3), P3r = lane_right(P3);
+            const float M2l = lane_left(M2), M3l = lane_left(M3);
+            const bool keep = (W4l | W4 | W3l | W3) != 0;
+            const float fill = 0.25f * (M3l + M3 + M2l + M2);
+            const float sm = (I > 0 ? P3l : P3) + (I < nx ? P3r : P3) + (Y > 0 ? P4 : P3) + (Y < ny ? P2 : P3);
+            const float out = keep ? (INIT ? P3 : wp * P3 + wq * sm) : fill;
+            if (store & (Y <= ny)) stf(Hout, (uint32_t)Y * nxc + (uint32_t)I, out);
         }
-    }
-    for (int idx = tid; idx < WMR * WMC; idx += RTHREADS) {
-        int r = idx / WMC, c = idx - r * WMC;
-        int j = J0 - 3 + r, i = I0 - 3 + c;
-        bool in = j >= 0 && j < ny && i >= 0 && i < nx;
-        uint32_t k = in ? (uint32_t)j * (uint32_t)nx + (uint32_t)i : 0u;
-        sM[r][c] = in ? Hm[k] : 0.0f;
-        sW[r][c] = in && (land == nullptr || land[k] == 0);
-    }
-    __syncthreads();
 
-    for (int idx = tid; idx < WMR * WMC; idx += RTHREADS) {
-        int r = idx / WMC, c = idx - r * WMC;
-        float d = 0.0f;
-        if (sW[r][c]) {
-            // a water cell lies inside the domain, so its four corners do too
-            d = INIT ? sM[r][c]
-                     : sM[r][c] - 0.25f * (sH[r][c] + sH[r][c + 1] + sH[r + 1][c] + sH[r + 1][c + 1]);
-        }
-        sD[r][c] = d;
+        H2 = H1; H1 = Ha; H1r = Har;
+        D3 = D2; D2 = D1;
+        W4 = W3; W3 = W2; W2 = W1; W4l = W3l; W3l = W2l;
+        UR3 = UR2; UL3 = UL2;
+        P4 = P3; P3 = P2;
+        M3 = M2; M2 = M1; M1 = Mc;
     }
-    __syncthreads();
+}
 
-    // limited slopes (cell units); a difference toward a non-water cell is 0
-    for (int idx = tid; idx < WMR * WMC; idx += RTHREADS) {
-        int r = idx / WMC, c = idx - r * WMC;
-        float sx = 0.0f, sy = 0.0f;
-        if (r >= 1 && r < WMR - 1 && c >= 1 && c < WMC - 1 && sW[r][c]) {
-            float v = sD[r][c];
-            float dl = sW[r][c - 1] ? v - sD[r][c - 1] : 0.0f;
-            float dr = sW[r][c + 1] ? sD[r][c + 1] - v : 0.0f;
-            float ds = sW[r - 1][c] ? v - sD[r - 1][c] : 0.0f;
-            float dn = sW[r + 1][c] ? sD[r + 1][c] - v : 0.0f;
-            sx = minmod2(dl, dr);
-            sy = minmod2(ds, dn);
-        }
-        sSx[r][c] = sx;
-        sSy[r][c] = sy;
-    }
-    __syncthreads();
-
-    // corner estimates: the planes of the (up to four) water cells at a
-    // corner, evaluated there and averaged (cells taken in row-major order)
-    for (int idx = tid; idx < (RTY + 2) * (RTX + 2); idx += RTHREADS) {
-        int r = 2 + idx / (RTX + 2), c = 2 + idx % (RTX + 2);
-        float acc = 0.0f;
-        int cnt = 0;
-        if (sW[r - 1][c - 1]) { acc += sD[r - 1][c - 1] + 0.5f * sSx[r - 1][c - 1] + 0.5f * sSy[r - 1][c - 1]; cnt++; }
-        if (sW[r - 1][c]) { acc += sD[r - 1][c] - 0.5f * sSx[r - 1][c] + 0.5f * sSy[r - 1][c]; cnt++; }
-        if (sW[r][c - 1]) { acc += sD[r][c - 1] + 0.5f * sSx[r][c - 1] - 0.5f * sSy[r][c - 1]; cnt++; }
-        if (sW[r][c]) { acc += sD[r][c] - 0.5f * sSx[r][c] - 0.5f * sSy[r][c]; cnt++; }
-        float est = cnt ? acc / (float)cnt : 0.0f;
-        sH[r][c] = INIT ? est : sH[r][c] + est;
-    }
-    __syncthreads();
-
-    for (int idx = tid; idx < RTY * RTX; idx += RTHREADS) {
-        int r = 3 + idx / RTX, c = 3 + idx % RTX;
-        int J = J0 - 3 + r, I = I0 - 3 + c;
-        if (J > ny || I > nx) continue;
-        bool keep = sW[r - 1][c - 1] | sW[r - 1][c] | sW[r][c - 1] | sW[r][c];
-        float out;
-        if (keep) {
-            float p = sH[r][c];
-            if (INIT) {
-                out = p;
-            } else {
-                float s = sH[r][I > 0 ? c - 1 : c] + sH[r][I < nx ? c + 1 : c] + sH[J > 0 ? r - 1 : r][c] +
-                          sH[J < ny ? r + 1 : r][c];
-                out = (1.0f - w) * p + 0.25f * w * s;
-            }
-        } else {
-            // cells (J-1, I-1), (J-1, I), (J, I-1), (J, I), clamped to the domain
-            int rs = J > 0 ? r - 1 : r, rn = J < ny ? r : r - 1;
-            int cw = I > 0 ? c - 1 : c, ce = I < nx ? c : c - 1;
-            out = 0.25f * (sM[rs][cw] + sM[rs][ce] + sM[rn][cw] + sM[rn][ce]);
-        }
-        Hout[(uint32_t)J * (uint32_t)nxc + (uint32_t)I] = out;
-    }
+template <bool INIT>
+hipError_t launch_recon_round(int R, unsigned blocks, hipStream_t s, int nx, int ny, int nsx, int items,
+                              const float *Hm, const uint8_t *land, const float *Hin, float w, float *Hout)
+{
+    if (R == 16)
+        hipLaunchKernelGGL((recon_round_kernel<INIT, 16>), dim3(blocks), dim3(256), 0, s, nx, ny, nsx, items, Hm,
+                           land, Hin, w, Hout);
+    else
+        hipLaunchKernelGGL((recon_round_kernel<INIT, 8>), dim3(blocks), dim3(256), 0, s, nx, ny, nsx, items, Hm,
+                           land, Hin, w, Hout);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -319,21 +345,22 @@ extern "C" int swe_reconstruct_bathymetry(int32_t nx, int32_t ny, const float *H
     if (iters > 0 && !scratch) return set_error(SWE_E_ARG, "scratch is required when iters > 0");
     if (!(smooth >= 0.0f && smooth <= 1.0f)) return set_error(SWE_E_ARG, "smooth must be in [0, 1]");
     hipStream_t s = (hipStream_t)hip_stream;
-    int nbx = (nx + 1 + RTX - 1) / RTX, nby = (ny + 1 + RTY - 1) / RTY;
-    int64_t tiles = (int64_t)nbx * nby;
-    if (tiles > INT32_MAX) return set_error(SWE_E_ARG, "domain too large");
+    // rows per segment: 16 when that still gives about four waves per SIMD,
+    // else 8 (more waves, more warm-up rows)
+    const int nsx = (nx + 1 + RSTRIP - 1) / RSTRIP;
+    const int R = (int64_t)nsx * ((ny + 1 + 15) / 16) >= 4096 ? 16 : 8;
+    const int nsy = (ny + 1 + R - 1) / R;
+    const int64_t items = (int64_t)nsx * nsy;
+    if (items > INT32_MAX / 2) return set_error(SWE_E_ARG, "domain too large");
+    const unsigned blocks = (unsigned)((items + 3) / 4);
     // round k writes Hc when iters - k is even, so the last round ends in Hc
     float *buf[2] = {Hc, scratch};
     float *cur = buf[iters & 1];
-    hipLaunchKernelGGL(recon_round_kernel<true>, dim3((unsigned)tiles), dim3(RTHREADS), 0, s, nx, ny, nbx, Hm,
-                       land, (const float *)nullptr, smooth, cur);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_recon_round<true>(R, blocks, s, nx, ny, nsx, (int)items, Hm, land, nullptr, smooth, cur);
     if (e != hipSuccess) return hip_error(e, "recon_round_kernel<init>");
     for (int k = 1; k <= iters; ++k) {
         float *nxt = buf[(iters - k) & 1];
-        hipLaunchKernelGGL(recon_round_kernel<false>, dim3((unsigned)tiles), dim3(RTHREADS), 0, s, nx, ny, nbx,
-                           Hm, land, (const float *)cur, smooth, nxt);
-        e = hipGetLastError();
+        e = launch_recon_round<false>(R, blocks, s, nx, ny, nsx, (int)items, Hm, land, cur, smooth, nxt);
         if (e != hipSuccess) return hip_error(e, "recon_round_kernel");
         cur = nxt;
     }

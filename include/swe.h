@@ -152,6 +152,21 @@ int swe_step_dt(swe_domain *d, int32_t n_steps, const double *dts);
  * non-finite. */
 int swe_run_until(swe_domain *d, double t_end, int64_t *steps_taken);
 
+/* Time-step update policy.  interval = 0 (the default): dt from eq. cfl at
+ * the start of every step.  interval > 0: the policy of the paper's
+ * real-world runs (section "Real-world simulations": dt updated every 20
+ * simulated minutes, Courant number 0.8) -- a step takes the dt
+ * of the last update until the time of the next update is reached; the step
+ * that starts at or after it takes the CFL dt of its state, and the next
+ * update moves one interval on (to one interval past that step's start if
+ * that is not later).  The first step after this call (or after
+ * swe_set_state) updates.  swe_run_until still clamps the last step to its
+ * end time; swe_step_dt ignores the policy.  The CFL maximum is still
+ * reduced every step (the state's wave speed stays observable).
+ * Errors: SWE_E_ARG (negative or non-finite interval), SWE_E_STATE (member
+ * of an ensemble), SWE_E_HIP.  Synchronises the stream. */
+int swe_set_dt_policy(swe_domain *d, double interval);
+
 /* Copy the state into caller buffers (each [ny][nx] float32; host or device
  * pointers, any may be NULL) and report time t and the dt of the next step.
  * Synchronises.  Returns SWE_E_UNSTABLE if the device flag is set. */

@@ -46,7 +46,7 @@ class _Params(C.Structure):
         ("wind_n", C.c_int32), ("wind_t", _D), ("wind_tau", _D),
         ("bnd_n", C.c_int32), ("bnd_t", _D), ("bnd", _D),
         ("w10_n", C.c_int32), ("w10_nx", C.c_int32), ("w10_ny", C.c_int32),
-        ("w10_t", _D), ("w10", _D), ("rho_a", C.c_double),
+        ("w10_t", _D), ("w10", _D), ("rho_a", C.c_double), ("dt_interval", C.c_double),
     ]
 
 
@@ -155,6 +155,7 @@ class Oracle:
             p.w10_n, p.w10_ny, p.w10_nx = wd.shape[0], wd.shape[1], wd.shape[2]
             p.w10_t, p.w10 = _dp(wt), _dp(wd)
         p.rho_a = float(getattr(wl, "rho_a", 1.225))
+        p.dt_interval = float(getattr(wl, "dt_interval", 0.0))
         self.p = p
         s = _Static()
         s.Hc, s.f, s.north = _dp(self.Hc), _dp(self.f), _dp(self.north)

@@ -241,6 +241,7 @@ static int check_params(const or_params *p)
         if (p->bc[k] == OR_BC_NESTED && (p->bnd_n < 1 || !p->bnd || !p->bnd_t)) return -1;
     }
     if (p->w10_n > 0 && (p->w10_nx < 1 || p->w10_ny < 1 || !p->w10 || !p->w10_t || !(p->rho_a > 0))) return -1;
+    if (!(p->dt_interval >= 0.0)) return -1;
     return 0;
 }
 
@@ -673,12 +674,22 @@ int64_t or_run(const or_params *p, const or_static *s, double *eta, double *hu, 
     step_ws sw;
     if (step_ws_init(&sw, p->nx, p->ny)) return -2;
     int64_t k = 0;
+    double dt_hold = 0.0, t_upd = *t;  /* dt update policy state */
     for (; k < nsteps; ++k) {
         double dt;
         if (dt_fixed > 0.0) dt = dt_fixed;
         else if (dts) dt = dts[k];
         else {
-            dt = or_cfl_dt(p, s, eta, hu, hv);
+            if (p->dt_interval > 0.0 && dt_hold > 0.0 && *t < t_upd) {
+                dt = dt_hold;
+            } else {
+                dt = or_cfl_dt(p, s, eta, hu, hv);
+                if (p->dt_interval > 0.0) {
+                    dt_hold = dt;
+                    t_upd += p->dt_interval;
+                    if (t_upd <= *t) t_upd = *t + p->dt_interval;
+                }
+            }
             if (t_end > 0.0) {
                 if (*t >= t_end) break;
                 if (dt > t_end - *t) dt = t_end - *t;

@@ -46,6 +46,11 @@ typedef struct {
     int32_t w10_n, w10_nx, w10_ny;
     const double *w10_t, *w10;
     double rho_a;       /* density of air */
+    /* time-step update policy of section "Real-world simulations": 0 = the
+     * CFL dt every step; > 0 = the CFL dt only at the first step starting at
+     * or after each update time (the run's start, then one interval later
+     * each time), the last update's dt in between */
+    double dt_interval;
 } or_params;
 
 /* per-cell inputs of the problem statement */
@@ -86,7 +91,8 @@ int or_step(const or_params *p, const or_static *s, double *eta, double *hu, dou
 
 /* nsteps steps.  dt_fixed > 0: that dt every step; dts != NULL and
  * dt_fixed <= 0: replay dts[k]; otherwise dt from the CFL condition of the
- * state at the start of each step, clamped so that t never exceeds t_end
+ * state at the start of each step (or at update steps only, under the
+ * dt_interval policy), clamped so that t never exceeds t_end
  * when t_end > 0 (the run stops once t reaches t_end).  dts_out (optional)
  * receives the dt of each step.  Returns the number of steps taken, or a
  * negative code. */

@@ -593,8 +593,8 @@ int swe_run_until(swe_domain *d, double t_end, int64_t *steps_taken)
             t = c.t[d->parity];
             if (c.flags) break;
             if (t >= t_end) break;
-            float wm = ctrl_wmax(c, d->parity);
-            double dt = wm > 0 ? (double)(d->dom.courant_q / wm) : 1.0;
+            double dt = ctrl_next_dt(c, d->parity, d->dom.courant_q, d->dom.dt_interval);
+            if (!std::isfinite(dt)) dt = 1.0;
             double est = (t_end - t) / dt;
             int n = (int)std::min<double>(chunk_max, std::max<double>(kGraphChunk, std::ceil(est * 1.05) + 1));
             if ((rc = swe_step(d, n))) break;
@@ -634,11 +634,20 @@ int swe_read_state(swe_domain *d, float *eta, float *hu, float *hv, double *t, d
     for (int k = 0; k < 3; ++k)
         if (staged[k]) std::memcpy(dst[k], d->pinned_state + k * plane, plane * sizeof(float));
     if (t) *t = c.t[d->parity];
-    if (dt_next) {
-        float wm = ctrl_wmax(c, d->parity);
-        *dt_next = wm > 0 ? (double)(d->dom.courant_q / wm) : INFINITY;
-    }
+    if (dt_next) *dt_next = ctrl_next_dt(c, d->parity, d->dom.courant_q, d->dom.dt_interval);
     if (c.flags) return fail(SWE_E_UNSTABLE, "non-finite state");
+    return SWE_OK;
+}
+
+int swe_set_dt_policy(swe_domain *d, double interval)
+{
+    if (!d) return fail(SWE_E_ARG, "domain is NULL");
+    if (!(std::isfinite(interval) && interval >= 0.0)) return fail(SWE_E_ARG, "interval must be finite and >= 0");
+    if (d->ensemble) return fail(SWE_E_STATE, "domain belongs to an ensemble");
+    d->dom.dt_interval = interval;
+    drop_graphs(d);  // the graphs hold the domain block by value
+    HIP_TRY(launch_policy_reset(d->dom.ctrl, d->parity, d->stream));
+    HIP_TRY(hipStreamSynchronize(d->stream));
     return SWE_OK;
 }
 

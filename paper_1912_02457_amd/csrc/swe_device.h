@@ -40,7 +40,10 @@ struct Ctrl {
     int64_t steps;       // steps taken (no-op steps past t_end excluded)
     double t_end;        // > 0: clamp steps to end exactly at t_end, skip steps after it
     double mass, energy; // results of the diagnostics reduction
-    double pad[9];
+    // dt update policy (Dom::dt_interval > 0): dt held since the last update
+    // and the time of the next update, per parity like t
+    double dt_hold[2], t_upd[2];
+    double pad[5];
     // max over non-land cells of max((|u|+c)/dx, (|v|+c)/dy) as float bits, per parity
     uint32_t wslot[2][kCflSlots][kCflStride];
 };
@@ -55,6 +58,14 @@ inline float ctrl_wmax(const Ctrl &c, int parity)
     return f;
 }
 
+// host-side: the dt the next step of this parity takes (t_end clamp aside)
+inline double ctrl_next_dt(const Ctrl &c, int parity, float courant_q, double dt_interval)
+{
+    if (dt_interval > 0.0 && c.dt_hold[parity] > 0.0 && c.t[parity] < c.t_upd[parity]) return c.dt_hold[parity];
+    float wm = ctrl_wmax(c, parity);
+    return wm > 0 ? (double)(courant_q / wm) : INFINITY;
+}
+
 // Everything a stage kernel needs, passed by value.
 struct Dom {
     int nx, ny, pitch, cpitch, P;  // P = 2 ny + 2 nx perimeter cells
@@ -64,6 +75,7 @@ struct Dom {
     int friction;
     float fric_c;                  // r, r, or g n^2 (Manning)
     double inv_rho_w;
+    double dt_interval;            // > 0: dt re-evaluated only once this much time has passed
     double g64, kappa64, dx64, dy64;  // float64 copies for the diagnostics reductions
     int frs_w;
     float *eta, *hu, *hv;          // Q^n, updated in place by stage 2

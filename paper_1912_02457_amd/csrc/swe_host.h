@@ -19,6 +19,7 @@ hipError_t launch_ensemble(int stage, bool proj, bool w10, const EnsMember *mem,
 hipError_t launch_cfl(const Dom &d, int slot, hipStream_t s);
 hipError_t launch_ctrl_reset(Ctrl *c, double t, int slot, hipStream_t s);
 hipError_t launch_set_t_end(Ctrl *c, double te, hipStream_t s);
+hipError_t launch_policy_reset(Ctrl *c, int parity, hipStream_t s);
 hipError_t launch_diagnostics(const Dom &d, hipStream_t s);
 int stage_waves_per_simd(int stage, bool proj);
 int ensemble_waves_per_simd(int stage, bool proj);

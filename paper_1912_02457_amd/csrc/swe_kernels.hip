@@ -697,6 +697,7 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
 // ---------------------------------------------------------------------------
 struct StepTime {
     double tn, dtd;
+    double hold, tupd;  // dt update policy state after this step
     uint32_t wbits;
     bool skip, last;
 };
@@ -709,6 +710,20 @@ __device__ __forceinline__ StepTime step_time(const Dom &d, int parity, double d
     s.wbits = read_wmax(ctrl, parity, lane);
     const double te = ctrl->t_end;
     s.dtd = dt_fixed > 0.0 ? dt_fixed : (double)(d.courant_q / __uint_as_float(s.wbits));
+    // dt update policy: keep the dt of the last update until the update time
+    // is reached, then take the CFL dt and move the update time on by one
+    // interval (to one interval past t^n if that is not enough)
+    s.hold = ctrl->dt_hold[parity];
+    s.tupd = ctrl->t_upd[parity];
+    if (dt_fixed <= 0.0 && d.dt_interval > 0.0) {
+        if (s.hold > 0.0 && s.tn < s.tupd) {
+            s.dtd = s.hold;
+        } else {
+            s.hold = s.dtd;
+            s.tupd += d.dt_interval;
+            if (s.tupd <= s.tn) s.tupd = s.tn + d.dt_interval;
+        }
+    }
     s.skip = false;
     s.last = false;
     if (te > 0.0) {
@@ -725,6 +740,10 @@ __device__ __forceinline__ void advance_ctrl(Ctrl *ctrl, const StepTime &s, int 
 {
     if (lane < kCflSlots) ctrl->wslot[parity ^ 1][lane][0] = s.skip ? s.wbits : 0u;
     if (lane == 0) {
+        // a skipped step keeps the policy state; a step clamped to t_end
+        // records the dt it would have taken
+        ctrl->dt_hold[parity ^ 1] = s.skip ? ctrl->dt_hold[parity] : s.hold;
+        ctrl->t_upd[parity ^ 1] = s.skip ? ctrl->t_upd[parity] : s.tupd;
         if (s.skip) {
             ctrl->t[parity ^ 1] = s.tn;
         } else {
@@ -907,7 +926,18 @@ __global__ void ctrl_reset_kernel(Ctrl *c, double t, int slot)
             c->flags = 0u;
             c->dt_last = 0.f;
             c->t_end = 0.0;
+            c->dt_hold[0] = c->dt_hold[1] = 0.0;
+            c->t_upd[0] = c->t_upd[1] = t;
         }
+    }
+}
+
+// dt update policy restarted at the current time of the given parity
+__global__ void ctrl_policy_reset_kernel(Ctrl *c, int parity)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->dt_hold[0] = c->dt_hold[1] = 0.0;
+        c->t_upd[0] = c->t_upd[1] = c->t[parity];
     }
 }
 
@@ -1078,6 +1108,12 @@ hipError_t launch_cfl(const Dom &d, int slot, hipStream_t s)
 hipError_t launch_ctrl_reset(Ctrl *c, double t, int slot, hipStream_t s)
 {
     ctrl_reset_kernel<<<1, 64, 0, s>>>(c, t, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_policy_reset(Ctrl *c, int parity, hipStream_t s)
+{
+    ctrl_policy_reset_kernel<<<1, 64, 0, s>>>(c, parity);
     return hipGetLastError();
 }
 

@@ -77,6 +77,7 @@ SIGNATURES = {
                                      C.c_size_t]),
     "swe_step": (C.c_int, [_VP, C.c_int32]),
     "swe_step_dt": (C.c_int, [_VP, C.c_int32, _D]),
+    "swe_set_dt_policy": (C.c_int, [_VP, C.c_double]),
     "swe_run_until": (C.c_int, [_VP, C.c_double, C.POINTER(C.c_int64)]),
     "swe_read_state": (C.c_int, [_VP, _VP, _VP, _VP, _D, _D]),
     "swe_set_state": (C.c_int, [_VP, _F, _F, _F, C.c_double]),
@@ -220,6 +221,8 @@ class Domain:
             dom.set_boundary(wl.bnd_t, wl.bnd)
         if getattr(wl, "w10", None) is not None:
             dom.set_wind_field(wl.w10_t, wl.w10, rho_air=getattr(wl, "rho_a", 1.225))
+        if getattr(wl, "dt_interval", 0.0) > 0.0:
+            dom.set_dt_policy(wl.dt_interval)
         return dom
 
     # -- forcing -----------------------------------------------------------
@@ -258,6 +261,11 @@ class Domain:
     # -- time stepping -----------------------------------------------------
     def step(self, n: int = 1):
         _check(load_library().swe_step(self._h, int(n)))
+
+    def set_dt_policy(self, interval: float = 0.0):
+        """dt from the CFL condition every step (0) or only once every
+        ``interval`` simulated seconds (``swe_set_dt_policy``)."""
+        _check(load_library().swe_set_dt_policy(self._h, float(interval)))
 
     def step_dt(self, dts):
         d = np.ascontiguousarray(np.asarray(dts, dtype=np.float64))

@@ -223,3 +223,8 @@ def test_preprocess_rejects_invalid_arguments(lib):
     assert cs(4, 0, 1, p, None, p, None, None, None, None) == E
     assert cs(4, 4, 1, p, None, p, p, None, None, None) == E             # land_out without land
     assert cs(4, 4, 0, None, None, None, None, p, None, None) == E
+
+
+def test_dt_policy_rejects_null_domain(lib):
+    from paper_1912_02457_amd import swe
+    assert lib.swe_set_dt_policy(None, 1200.0) == swe.SWE_E_ARG

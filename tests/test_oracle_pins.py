@@ -714,6 +714,47 @@ def test_run_until_lands_on_t_end():
     assert dts[-1] <= dts[0] * 1.5 and np.all(dts > 0)
 
 
+def _policy_updates(dts, t0, interval):
+    """Steps at which the policy of section "Real-world simulations" must
+    re-evaluate dt: the first step, then the first step starting at or after
+    each update time, which moves one interval on each time."""
+    t, nxt, out = t0, t0, []
+    for k, dt in enumerate(dts):
+        up = k == 0 or t >= nxt
+        out.append(up)
+        if up:
+            nxt = nxt + interval if nxt + interval > t else t + interval
+        t += dt
+    return np.array(out)
+
+
+def test_dt_policy_every_interval():
+    """Section "Real-world simulations": the time step is updated from eq. cfl
+    every 20 simulated minutes.  Scaled down (a 40 s interval over ~430 s of a
+    spreading bump): dt is held between updates, and at each update step it
+    equals the CFL step of the state at that step; the held value changes
+    from one update to the next."""
+    wl = make_wl(100.0, np.zeros((48, 48)), dx=1000.0, courant=0.45)
+    j, i = np.mgrid[0:48, 0:48]
+    wl = wl.copy(eta=1.5 * np.exp(-((i - 24.0) ** 2 + (j - 24.0) ** 2) / 18.0), dt_interval=40.0)
+    o = O.Oracle(wl)
+    _, t_end, dts, k = o.run(nsteps=120)
+    assert k == 120
+    up = _policy_updates(dts, 0.0, 40.0)
+    assert 8 <= up.sum() <= 12
+    assert np.all(dts[1:][~up[1:]] == dts[:-1][~up[1:]])          # held between updates
+    assert len(set(dts[up].tolist())) == up.sum()                  # and re-evaluated at each update
+    state, t = o.initial_state(), 0.0
+    for n in range(120):
+        if up[n]:
+            assert dts[n] == o.cfl_dt(state), n
+        state, t = o.step(state, t, dts[n])
+    # an interval below every step size updates every step: the plain rule
+    (e1, u1, v1), t1, d1, _ = O.Oracle(wl.copy(dt_interval=0.0)).run(nsteps=40)
+    (e2, u2, v2), t2, d2, _ = O.Oracle(wl.copy(dt_interval=1e-3)).run(nsteps=40)
+    assert np.array_equal(d1, d2) and np.array_equal(e1, e2) and t1 == t2
+
+
 def _conv_errors(levels, ref_N, mod=lambda w: w):
     ref = mod(convergence_case(ref_N))
     (re, ru, rv), *_ = O.Oracle(ref).run(nsteps=ref.steps, dt_fixed=ref.dt_fixed)

@@ -71,6 +71,9 @@ class Workload:
     w10_t: Optional[np.ndarray] = None
     w10: Optional[np.ndarray] = None
     rho_a: float = 1.225
+    # > 0: dt from the CFL condition only once every dt_interval seconds
+    # (the real-world runs' policy); 0: every step
+    dt_interval: float = 0.0
     steps: int = 1
     dt_fixed: Optional[float] = None
     t_end: Optional[float] = None

@@ -501,6 +501,7 @@ int swe_set_wind_field(swe_domain *d, int32_t n_times, int32_t nx_w, int32_t ny_
     if (d->ensemble) return fail(SWE_E_STATE, "domain belongs to an ensemble");
     if (n_times == 0) {
         d->dom.w10n = 0;
+        drop_graphs(d);  // the graphs hold the domain block by value
         return SWE_OK;
     }
     size_t need = 0;
@@ -761,14 +762,18 @@ int swe_autotune_tiling(swe_domain *d, int32_t *rows_per_wave)
     for (int k = 0; k < 3; ++k)
         HIP_TRY(hipMemcpy2DAsync(d->pinned_state + k * plane, row, q[k], dp, row, ny, hipMemcpyDeviceToHost, d->stream));
     int by1 = 0, by2 = 0;
-    if ((rc = sweep_stage(d, 1, &by1))) return rc;
-    HIP_TRY(launch_stage(1, d->p.north_projection != 0, d->dom, make_tiling(nx, ny, by1), d->parity, 0.0, d->stream,
-                         nullptr, nullptr));
-    if ((rc = sweep_stage(d, 2, &by2))) return rc;
+    rc = sweep_stage(d, 1, &by1);
+    if (!rc) {
+        hipError_t e = launch_stage(1, d->p.north_projection != 0, d->dom, make_tiling(nx, ny, by1), d->parity, 0.0,
+                                    d->stream, nullptr, nullptr);
+        rc = e != hipSuccess ? hip_fail(e, "launch_stage") : sweep_stage(d, 2, &by2);
+    }
+    // the state and control block go back even when the sweep failed
     for (int k = 0; k < 3; ++k)
         HIP_TRY(hipMemcpy2DAsync(q[k], dp, d->pinned_state + k * plane, row, row, ny, hipMemcpyHostToDevice, d->stream));
     HIP_TRY(hipMemcpyAsync(d->dom.ctrl, &saved, sizeof(Ctrl), hipMemcpyHostToDevice, d->stream));
     HIP_TRY(hipStreamSynchronize(d->stream));
+    if (rc) return rc;
     d->T[0] = make_tiling(nx, ny, by1);
     d->T[1] = make_tiling(nx, ny, by2);
     drop_graphs(d);
@@ -820,7 +825,7 @@ int swe_stage_times(swe_domain *d, double *ms_stage1, double *ms_stage2, int64_t
 void swe_destroy(swe_domain *d)
 {
     if (!d) return;
-    if (d->stream) (void)hipStreamSynchronize(d->stream);
+    (void)hipStreamSynchronize(d->stream);  // NULL: the null stream
     if (d->ensemble) ensemble_forget(d->ensemble, d);
     for (auto &kv : d->graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto g : d->graph_objs) (void)hipGraphDestroy(g);

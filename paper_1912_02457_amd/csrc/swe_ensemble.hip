@@ -320,7 +320,7 @@ int swe_ensemble_stage_times(swe_ensemble *e, double *ms1, double *ms2, int64_t 
 void swe_ensemble_destroy(swe_ensemble *e)
 {
     if (!e) return;
-    if (e->stream) (void)hipStreamSynchronize(e->stream);
+    (void)hipStreamSynchronize(e->stream);  // NULL: the null stream
     for (auto &kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto g : e->graph_objs) (void)hipGraphDestroy(g);
     for (auto ev : e->ev_pool) (void)hipEventDestroy(ev);

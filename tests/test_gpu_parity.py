@@ -131,6 +131,28 @@ def test_gridded_wind_matches_oracle(case):
     assert parity(off, ref)["hu_l2"] > 5e-4
 
 
+def test_forcing_changes_reach_replayed_graphs():
+    """Step graphs captured with a wind field are dropped when the field is
+    removed or the dt policy set: graph replay (16-step chunks) equals
+    one-by-one launches bitwise after each change."""
+    wl = add_wind_field(random_small(97, 83, seed=33), 5, 4, [0.0, 60.0], seed=5).copy(w10=None, w10_t=None)
+    field = add_wind_field(random_small(97, 83, seed=33), 5, 4, [0.0, 60.0], seed=5)
+    out = []
+    for eager in (False, True):
+        d = _dom(wl)
+        d.enable_timing(eager)  # timing mode launches every step eagerly
+        d.set_wind_field(field.w10_t, field.w10)
+        d.step(32)
+        d.set_wind_field(None, None)
+        d.step(32)
+        d.set_dt_policy(20.0)
+        d.step(32)
+        out.append(d.read_state())
+        d.close()
+    for x, y in zip(out[0][:4], out[1][:4]):
+        assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("proj", [False, True])
 def test_rossby_beta_plane_matches_oracle(proj):
     """The beta-plane Rossby-wave case of section "Coriolis force" (350 x 350

@@ -133,6 +133,17 @@ int swe_wind_field_bytes(int32_t n_times, int32_t nx_w, int32_t ny_w, size_t *by
 int swe_set_wind_field(swe_domain *d, int32_t n_times, int32_t nx_w, int32_t ny_w, const double *times,
                        const float *w10, double rho_air, void *dev_buffer, size_t bytes);
 
+/* The same grid, interpolation and buffer rules for a field of wind STRESS:
+ * tau (N/m^2) at the samples, [n_times][ny_w][nx_w][2], interpolated
+ * bilinearly in space and linearly in time as it is and divided by rho_w.
+ * The section calls the interpolated quantity both the wind and the wind
+ * stress; swe_set_wind_field interpolates the wind and takes the stress per
+ * cell, this call takes the stress at the samples.  One gridded field at a
+ * time: this replaces a wind field and the other way round; n_times = 0
+ * removes it.  Errors as swe_set_wind_field. */
+int swe_set_stress_field(swe_domain *d, int32_t n_times, int32_t nx_w, int32_t ny_w, const double *times,
+                         const float *tau, void *dev_buffer, size_t bytes);
+
 /* Advance n_steps SSP-RK2 steps (eq. rk2_semiimp with the spatial operator of
  * eq. sw_semidiscrete), each with the dt of eq. cfl computed on the device
  * from the state at the start of the step.  Asynchronous: no host

@@ -47,6 +47,7 @@ class _Params(C.Structure):
         ("bnd_n", C.c_int32), ("bnd_t", _D), ("bnd", _D),
         ("w10_n", C.c_int32), ("w10_nx", C.c_int32), ("w10_ny", C.c_int32),
         ("w10_t", _D), ("w10", _D), ("rho_a", C.c_double), ("dt_interval", C.c_double),
+        ("w10_kind", C.c_int32),
     ]
 
 
@@ -156,6 +157,7 @@ class Oracle:
             p.w10_t, p.w10 = _dp(wt), _dp(wd)
         p.rho_a = float(getattr(wl, "rho_a", 1.225))
         p.dt_interval = float(getattr(wl, "dt_interval", 0.0))
+        p.w10_kind = int(getattr(wl, "w10_kind", 0))
         self.p = p
         s = _Static()
         s.Hc, s.f, s.north = _dp(self.Hc), _dp(self.f), _dp(self.north)

@@ -129,7 +129,7 @@ static void wind_at(const or_params *p, double tau, double *tx, double *ty)
  * the two snapshots around tau (eq. windstress_interpol), bilinear in space
  * with the samples at the centres of a w10_nx x w10_ny partition of the
  * domain and clamped at its edges (what a texture fetch with linear
- * filtering returns), then the stress of Large and Pond,
+ * filtering returns), then (w10_kind 0) the stress of Large and Pond,
  *   tau / rho_w = (rho_a / rho_w) C_D |W| W,
  *   C_D = 1.2e-3 for |W| < 11 m/s, (0.49 + 0.065 |W|) 1e-3 above,
  * returned as the kinematic source of the momentum equations. */
@@ -164,6 +164,11 @@ static void w10_stress(const or_params *p, int i, int j, double tau, double *sx,
     double W[2];
     for (int c = 0; c < 2; ++c)
         W[c] = (1.0 - s) * w10_sample(p, k, gx, gy, c) + s * w10_sample(p, kb, gx, gy, c);
+    if (p->w10_kind == 1) {  /* a stress field: interpolated as it is */
+        *sx = W[0] / p->rho_w;
+        *sy = W[1] / p->rho_w;
+        return;
+    }
     double speed = sqrt(W[0] * W[0] + W[1] * W[1]);
     double cd = speed < 11.0 ? 1.2e-3 : (0.49 + 0.065 * speed) * 1e-3;
     double q = p->rho_a / p->rho_w * cd * speed;
@@ -242,6 +247,7 @@ static int check_params(const or_params *p)
     }
     if (p->w10_n > 0 && (p->w10_nx < 1 || p->w10_ny < 1 || !p->w10 || !p->w10_t || !(p->rho_a > 0))) return -1;
     if (!(p->dt_interval >= 0.0)) return -1;
+    if (p->w10_kind != 0 && p->w10_kind != 1) return -1;
     return 0;
 }
 

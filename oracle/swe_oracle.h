@@ -51,6 +51,10 @@ typedef struct {
      * or after each update time (the run's start, then one interval later
      * each time), the last update's dt in between */
     double dt_interval;
+    /* what the gridded field holds: 0 = wind at 10 m in m/s, the stress of
+     * Large and Pond taken from the wind interpolated to each cell; 1 = wind
+     * stress in N/m^2 at the samples, interpolated as it is */
+    int32_t w10_kind;
 } or_params;
 
 /* per-cell inputs of the problem statement */

@@ -494,8 +494,11 @@ int swe_wind_field_bytes(int32_t n_times, int32_t nx_w, int32_t ny_w, size_t *by
     return SWE_OK;
 }
 
-int swe_set_wind_field(swe_domain *d, int32_t n_times, int32_t nx_w, int32_t ny_w, const double *times,
-                       const float *w10, double rho_air, void *dev_buffer, size_t bytes)
+namespace {
+
+// Gridded wind (kind 0, with rho_air) or gridded stress (kind 1).
+int set_field(swe_domain *d, int kind, int32_t n_times, int32_t nx_w, int32_t ny_w, const double *times,
+              const float *w10, double rho_air, void *dev_buffer, size_t bytes)
 {
     if (!d) return fail(SWE_E_ARG, "domain is NULL");
     if (d->ensemble) return fail(SWE_E_STATE, "domain belongs to an ensemble");
@@ -534,10 +537,25 @@ int swe_set_wind_field(swe_domain *d, int32_t n_times, int32_t nx_w, int32_t ny_
     D.w10ny = ny_w;
     D.w10sx = (float)((double)nx_w / d->p.nx);
     D.w10sy = (float)((double)ny_w / d->p.ny);
-    D.w10q = (float)(rho_air / d->p.rho_w);
+    D.w10q = (float)((kind == 0 ? rho_air : 1.0) / d->p.rho_w);
+    D.w10_kind = kind;
     D.w10n = n_times;
     drop_graphs(d);  // the graphs hold the domain block by value
     return SWE_OK;
+}
+
+}  // namespace
+
+int swe_set_wind_field(swe_domain *d, int32_t n_times, int32_t nx_w, int32_t ny_w, const double *times,
+                       const float *w10, double rho_air, void *dev_buffer, size_t bytes)
+{
+    return set_field(d, 0, n_times, nx_w, ny_w, times, w10, rho_air, dev_buffer, bytes);
+}
+
+int swe_set_stress_field(swe_domain *d, int32_t n_times, int32_t nx_w, int32_t ny_w, const double *times,
+                         const float *tau, void *dev_buffer, size_t bytes)
+{
+    return set_field(d, 1, n_times, nx_w, ny_w, times, tau, 1.0, dev_buffer, bytes);
 }
 
 int swe_step(swe_domain *d, int32_t n_steps)

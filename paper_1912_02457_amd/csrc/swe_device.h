@@ -91,7 +91,8 @@ struct Dom {
     const float *wind;             // [nw][2]
     int w10n, w10nx, w10ny;        // wind at 10 m on its own grid: snapshots, samples (0 = none)
     float w10sx, w10sy;            // samples per cell along x and y
-    float w10q;                    // rho_air / rho_w
+    float w10q;                    // rho_air / rho_w (wind at 10 m) or 1 / rho_w (stress field)
+    int w10_kind;                  // 0: wind at 10 m, stress of Large and Pond per cell; 1: stress field
     const double *w10_t;
     const float *w10;              // [w10n][w10ny][w10nx][2] m/s
     Ctrl *ctrl;

@@ -377,6 +377,11 @@ __device__ __forceinline__ void w10_stress(const Dom &d, const TileCtx &c, float
                   fy * ((1.f - fx) * at(Wb, i0, j1) + fx * at(Wb, i1, j1));
         W[q] = (1.f - c.ws) * a + c.ws * b;
     }
+    if (d.w10_kind) {  // a stress field, interpolated as it is
+        sx = d.w10q * W[0];
+        sy = d.w10q * W[1];
+        return;
+    }
     const float sp = fsqrt(W[0] * W[0] + W[1] * W[1]);
     const float cd = sp < 11.f ? 1.2e-3f : (0.49f + 0.065f * sp) * 1e-3f;
     const float k = d.w10q * cd * sp;

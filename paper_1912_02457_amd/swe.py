@@ -75,6 +75,7 @@ SIGNATURES = {
     "swe_wind_field_bytes": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "swe_set_wind_field": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _D, _F, C.c_double, _VP,
                                      C.c_size_t]),
+    "swe_set_stress_field": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _D, _F, _VP, C.c_size_t]),
     "swe_step": (C.c_int, [_VP, C.c_int32]),
     "swe_step_dt": (C.c_int, [_VP, C.c_int32, _D]),
     "swe_set_dt_policy": (C.c_int, [_VP, C.c_double]),
@@ -220,7 +221,8 @@ class Domain:
         if wl.bnd is not None:
             dom.set_boundary(wl.bnd_t, wl.bnd)
         if getattr(wl, "w10", None) is not None:
-            dom.set_wind_field(wl.w10_t, wl.w10, rho_air=getattr(wl, "rho_a", 1.225))
+            dom.set_wind_field(wl.w10_t, wl.w10, rho_air=getattr(wl, "rho_a", 1.225),
+                               kind=getattr(wl, "w10_kind", 0))
         if getattr(wl, "dt_interval", 0.0) > 0.0:
             dom.set_dt_policy(wl.dt_interval)
         return dom
@@ -238,9 +240,11 @@ class Domain:
         _check(load_library().swe_set_forcing(self._h, FORCING_BOUNDARY, len(t),
                                               t.ctypes.data_as(_D), _fp(d)))
 
-    def set_wind_field(self, times, w10, rho_air: float = 1.225):
-        """Wind at 10 m on its own grid, array [n_times][ny_w][nx_w][2] in m/s
-        (Large and Pond stress, trilinear interpolation); None removes it."""
+    def set_wind_field(self, times, w10, rho_air: float = 1.225, kind: int = 0):
+        """A field on its own grid, array [n_times][ny_w][nx_w][2]: wind at
+        10 m in m/s (kind 0, Large and Pond stress per cell,
+        ``swe_set_wind_field``) or wind stress in N/m^2 (kind 1,
+        ``swe_set_stress_field``); trilinear interpolation; None removes it."""
         import torch
         L = load_library()
         if w10 is None:
@@ -254,8 +258,14 @@ class Domain:
         n = C.c_size_t()
         _check(L.swe_wind_field_bytes(len(t), w.shape[2], w.shape[1], C.byref(n)))
         buf = torch.empty(n.value, dtype=torch.uint8, device=self.device)
-        _check(L.swe_set_wind_field(self._h, len(t), w.shape[2], w.shape[1], t.ctypes.data_as(_D), _fp(w),
-                                    float(rho_air), C.c_void_p(buf.data_ptr()), n.value))
+        if kind == 1:
+            _check(L.swe_set_stress_field(self._h, len(t), w.shape[2], w.shape[1], t.ctypes.data_as(_D), _fp(w),
+                                          C.c_void_p(buf.data_ptr()), n.value))
+        elif kind == 0:
+            _check(L.swe_set_wind_field(self._h, len(t), w.shape[2], w.shape[1], t.ctypes.data_as(_D), _fp(w),
+                                        float(rho_air), C.c_void_p(buf.data_ptr()), n.value))
+        else:
+            raise ValueError("kind must be 0 (wind at 10 m) or 1 (stress)")
         self.wind_field = buf  # borrowed by the library until replaced
 
     # -- time stepping -----------------------------------------------------

@@ -131,6 +131,25 @@ def test_gridded_wind_matches_oracle(case):
     assert parity(off, ref)["hu_l2"] > 5e-4
 
 
+def test_stress_field_matches_oracle():
+    """A gridded wind-stress field (N/m^2 at the samples, interpolated as it
+    is) on walls + land, 60 steps against the oracle; the same numbers read as
+    wind at 10 m give a different run."""
+    wl = add_wind_field(random_small(97, 83, seed=34, land_frac=0.15), 6, 5, [0.0, 40.0, 80.0], seed=6)
+    W = wl.w10.astype(np.float64)
+    sp = np.hypot(W[..., 0], W[..., 1])[..., None]
+    wl = wl.copy(w10=(1.5e-3 * 1.225 * sp * W).astype(np.float32), w10_kind=1)
+    _say("stress field")
+    ref, t_ref, rep, own = run_both(wl, 60)
+    assert_parity(rep, ref, label="stress field dt-replay")
+    assert_parity(own, ref, label="stress field own-dt")
+    d = _dom(wl.copy(w10_kind=0))
+    d.step_dt(O.Oracle(wl).run(nsteps=60)[2])
+    other = d.read_state()
+    d.close()
+    assert parity(other, ref)["hu_l2"] > 5e-4
+
+
 def test_forcing_changes_reach_replayed_graphs():
     """Step graphs captured with a wind field are dropped when the field is
     removed or the dt policy set: graph replay (16-step chunks) equals

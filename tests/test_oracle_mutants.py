@@ -43,6 +43,8 @@ MUTANTS = {
                                   "W[c] = s * w10_sample(p, k, gx, gy, c) + (1.0 - s) * w10_sample(p, kb, gx, gy, c);"),
     "dt_policy_never_updates": ("                    t_upd += p->dt_interval;\n", "                    t_upd += 1e30;\n"),
     "dt_policy_hold_not_kept": ("                    dt_hold = dt;\n", ""),
+    "stress_field_through_large_pond": ("    if (p->w10_kind == 1) {  /* a stress field: interpolated as it is */",
+                                        "    if (0) {"),
     "wind_samples_at_corners": ("double gx = (i + 0.5) * p->w10_nx / (double)p->nx - 0.5;",
                                 "double gx = (i + 0.5) * (p->w10_nx - 1) / (double)p->nx;"),
 }

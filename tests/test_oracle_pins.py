@@ -549,6 +549,31 @@ def test_w10_uniform_field_equals_stress_forcing(W):
     np.testing.assert_allclose(ra[1], 0.5 + float(sx) * 100.0, rtol=1e-13)
 
 
+def test_stress_field_uniform_and_interpolated_as_is():
+    """The second reading of section "Wind" (the stress given at the samples
+    and interpolated): a uniform stress field equals the uniform stress path;
+    a field varying in time gives the time-interpolated stress at each stage
+    (the source is linear in time, so RK2 integrates it exactly); and the
+    same numbers read as wind at 10 m give the Large and Pond stress
+    instead."""
+    base = _uniform(nx=10, ny=7, hu=0.5, hv=-0.2)
+    tau = np.empty((1, 3, 4, 2))
+    tau[..., 0], tau[..., 1] = 0.3, -0.12
+    a = base.copy(w10_t=np.array([0.0]), w10=tau, w10_kind=1)
+    b = base.copy(wind_t=np.array([0.0]), wind_tau=np.array([[0.3, -0.12]]))
+    ra = O.Oracle(a).run(nsteps=20, dt_fixed=5.0)[0]
+    rb = O.Oracle(b).run(nsteps=20, dt_fixed=5.0)[0]
+    for x, y in zip(ra, rb):
+        np.testing.assert_allclose(x, y, rtol=1e-13, atol=1e-16)
+    # linear in time: tau_x(t) = 0.3 + 0.3 t / 100 -> hu(100) = 0.5 + (0.3*100 + 0.15*100) / 1025
+    tau2 = np.stack([tau[0], tau[0] * 2.0])
+    c = base.copy(w10_t=np.array([0.0, 100.0]), w10=tau2, w10_kind=1)
+    rc = O.Oracle(c).run(nsteps=20, dt_fixed=5.0)[0]
+    np.testing.assert_allclose(rc[1], 0.5 + (0.3 * 100.0 + 0.5 * 0.3 * 100.0) / 1025.0, rtol=1e-13)
+    rw = O.Oracle(a.copy(w10_kind=0)).run(nsteps=20, dt_fixed=5.0)[0]
+    assert np.abs(rw[1] - ra[1]).max() > 1e-3
+
+
 def test_w10_bilinear_in_space_and_linear_in_time():
     """Samples sit at the centres of an nx_w x ny_w partition of the domain
     and are interpolated bilinearly (exact for a field linear in x and y

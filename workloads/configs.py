@@ -71,6 +71,8 @@ class Workload:
     w10_t: Optional[np.ndarray] = None
     w10: Optional[np.ndarray] = None
     rho_a: float = 1.225
+    # 0: w10 holds wind at 10 m (m/s); 1: it holds wind stress (N/m^2)
+    w10_kind: int = 0
     # > 0: dt from the CFL condition only once every dt_interval seconds
     # (the real-world runs' policy); 0: every step
     dt_interval: float = 0.0

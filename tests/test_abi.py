@@ -228,3 +228,8 @@ def test_preprocess_rejects_invalid_arguments(lib):
 def test_dt_policy_rejects_null_domain(lib):
     from paper_1912_02457_amd import swe
     assert lib.swe_set_dt_policy(None, 1200.0) == swe.SWE_E_ARG
+
+
+def test_stress_field_rejects_invalid_arguments(lib):
+    from paper_1912_02457_amd import swe
+    assert lib.swe_set_stress_field(None, 1, 2, 2, None, None, None, 0) == swe.SWE_E_ARG

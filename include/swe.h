@@ -116,6 +116,22 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
 int swe_set_forcing(swe_domain *d, int32_t kind, int32_t n_times, const double *times,
                     const float *data);
 
+/* Boundary snapshots given at their own spacing (section "Nesting the
+ * model": boundary data interpolated linearly in time and space like the
+ * wind, so that it need not match the grid, e.g. after a refinement):
+ * data = n_times x 3 x (2 n_y + 2 n_x) for (eta, hu, hv) along the West side
+ * (n_y samples, south to north), East side, South side (n_x samples, west to
+ * east) and North side.  A side's samples sit at the centres of n equal
+ * parts of it; each boundary cell takes the linear interpolation at its
+ * centre (held at the end samples), once per snapshot, and the result is
+ * used as by swe_set_forcing(SWE_FORCING_BOUNDARY) (interpolation in space
+ * and in time are both linear, so the order does not matter).  n_x = nx and
+ * n_y = ny give the data unchanged.  Host arrays, copied; synchronises.
+ * Errors: SWE_E_ARG (counts, times, non-finite data, more snapshots than
+ * the workspace holds), SWE_E_STATE inside an ensemble, SWE_E_HIP. */
+int swe_set_boundary_field(swe_domain *d, int32_t n_times, int32_t n_x, int32_t n_y, const double *times,
+                           const float *data);
+
 /* Wind at 10 m on its own grid (section "Wind"): n_times snapshots at
  * increasing times of ny_w x nx_w samples of (u, v) in m/s, laid out
  * [n_times][ny_w][nx_w][2].  The samples sit at the centres of an nx_w x ny_w

@@ -120,6 +120,25 @@ def num_threads() -> int:
     return lib().or_num_threads()
 
 
+def resample_boundary(data, nx, ny, n_x, n_y):
+    """Boundary snapshots given at their own spacing (section "Nesting the
+    model": linear interpolation in space, like the wind) -> one value per
+    boundary cell.  data [n][3][2 n_y + 2 n_x] holds the W and E sides (n_y
+    samples each), then S and N (n_x); samples sit at the centres of equal
+    parts of a side, values outside the first/last centre are held.
+    Returns [n][3][2 ny + 2 nx]."""
+    data = np.asarray(data, np.float64)
+    out = np.empty(data.shape[:2] + (2 * ny + 2 * nx,))
+    parts = [(0, n_y, 0, ny), (n_y, n_y, ny, ny), (2 * n_y, n_x, 2 * ny, nx), (2 * n_y + n_x, n_x, 2 * ny + nx, nx)]
+    for a, n, b, m in parts:
+        xp = (np.arange(n) + 0.5) / n        # sample centres along the side (unit length)
+        x = (np.arange(m) + 0.5) / m          # cell centres
+        for t in range(data.shape[0]):
+            for f in range(3):
+                out[t, f, b:b + m] = np.interp(x, xp, data[t, f, a:a + n])
+    return out
+
+
 class Oracle:
     """Oracle bound to one workload's static inputs and forcing."""
 
@@ -145,7 +164,10 @@ class Oracle:
         p.wind_n, p.wind_t, p.wind_tau = len(wind_t), _dp(wind_t), _dp(wind_tau)
         if wl.bnd is not None:
             bt = self._hold("bnd_t", _f64(wl.bnd_t))
-            bd = self._hold("bnd", _f64(wl.bnd))
+            raw = _f64(wl.bnd)
+            if getattr(wl, "bnd_nx", 0) > 0:
+                raw = resample_boundary(raw, wl.nx, wl.ny, wl.bnd_nx, wl.bnd_ny)
+            bd = self._hold("bnd", raw)
             p.bnd_n, p.bnd_t, p.bnd = len(bt), _dp(bt), _dp(bd)
         else:
             p.bnd_n = 0

@@ -486,6 +486,39 @@ int swe_set_forcing(swe_domain *d, int32_t kind, int32_t n_times, const double *
     return SWE_OK;
 }
 
+int swe_set_boundary_field(swe_domain *d, int32_t n_times, int32_t n_x, int32_t n_y, const double *times,
+                           const float *data)
+{
+    if (!d || !times || !data || n_times < 1) return fail(SWE_E_ARG, "bad boundary-field arguments");
+    if (n_x < 1 || n_y < 1 || n_x > (1 << 28) || n_y > (1 << 28)) return fail(SWE_E_ARG, "bad sample counts");
+    if (n_times > d->max_bnd) return fail(SWE_E_ARG, "more boundary snapshots than the workspace holds");
+    const int nx = d->p.nx, ny = d->p.ny, P = 2 * nx + 2 * ny, Q = 2 * n_y + 2 * n_x;
+    if (!all_finite(data, (size_t)n_times * 3 * Q)) return fail(SWE_E_ARG, "non-finite boundary data");
+    // one side's samples sit at the centres of n equal parts of the side; a
+    // boundary cell takes the linear interpolation at its centre, clamped to
+    // the end samples (what a texture fetch with linear filtering returns)
+    auto side = [](const float *src, int n, float *dst, int m) {
+        for (int j = 0; j < m; ++j) {
+            double g = ((double)j + 0.5) * n / m - 0.5;
+            g = std::min(std::max(g, 0.0), (double)(n - 1));
+            int k0 = (int)g, k1 = std::min(k0 + 1, n - 1);
+            double w = g - k0;
+            dst[j] = (float)((1.0 - w) * src[k0] + w * src[k1]);
+        }
+    };
+    std::vector<float> cells((size_t)n_times * 3 * P);
+    for (int t = 0; t < n_times; ++t)
+        for (int f = 0; f < 3; ++f) {
+            const float *a = data + ((size_t)t * 3 + f) * Q;
+            float *o = cells.data() + ((size_t)t * 3 + f) * P;
+            side(a, n_y, o, ny);                        // West, by row
+            side(a + n_y, n_y, o + ny, ny);             // East
+            side(a + 2 * n_y, n_x, o + 2 * ny, nx);     // South, by column
+            side(a + 2 * n_y + n_x, n_x, o + 2 * ny + nx, nx);  // North
+        }
+    return swe_set_forcing(d, SWE_FORCING_BOUNDARY, n_times, times, cells.data());
+}
+
 int swe_wind_field_bytes(int32_t n_times, int32_t nx_w, int32_t ny_w, size_t *bytes)
 {
     if (!bytes || n_times < 1 || nx_w < 1 || ny_w < 1 || (int64_t)nx_w * ny_w > ((int64_t)1 << 26))

@@ -72,6 +72,7 @@ SIGNATURES = {
     "swe_init_domain": (C.c_int, [C.POINTER(Params), _VP, C.c_size_t, _VP, C.c_int32, C.c_int32,
                                   _F, _U8, _F, _F, _F, _F, _F, C.POINTER(_VP)]),
     "swe_set_forcing": (C.c_int, [_VP, C.c_int32, C.c_int32, _D, _F]),
+    "swe_set_boundary_field": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _D, _F]),
     "swe_wind_field_bytes": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "swe_set_wind_field": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _D, _F, C.c_double, _VP,
                                      C.c_size_t]),
@@ -219,7 +220,10 @@ class Domain:
                   max_bnd_times=max(nb, max_bnd_times or 0), device=device, stream=stream)
         dom.set_wind(wl.wind_t, wl.wind_tau)
         if wl.bnd is not None:
-            dom.set_boundary(wl.bnd_t, wl.bnd)
+            if getattr(wl, "bnd_nx", 0) > 0:
+                dom.set_boundary_field(wl.bnd_t, wl.bnd, wl.bnd_nx, wl.bnd_ny)
+            else:
+                dom.set_boundary(wl.bnd_t, wl.bnd)
         if getattr(wl, "w10", None) is not None:
             dom.set_wind_field(wl.w10_t, wl.w10, rho_air=getattr(wl, "rho_a", 1.225),
                                kind=getattr(wl, "w10_kind", 0))
@@ -239,6 +243,14 @@ class Domain:
         d = _f32(data, (len(t), 3, 2 * self.ny + 2 * self.nx))
         _check(load_library().swe_set_forcing(self._h, FORCING_BOUNDARY, len(t),
                                               t.ctypes.data_as(_D), _fp(d)))
+
+    def set_boundary_field(self, times, data, n_x: int, n_y: int):
+        """Boundary snapshots at their own spacing, [n_times][3][2 n_y + 2 n_x]
+        (``swe_set_boundary_field``)."""
+        t = np.ascontiguousarray(np.asarray(times, dtype=np.float64))
+        d = _f32(data, (len(t), 3, 2 * n_y + 2 * n_x))
+        _check(load_library().swe_set_boundary_field(self._h, len(t), int(n_x), int(n_y),
+                                                     t.ctypes.data_as(_D), _fp(d)))
 
     def set_wind_field(self, times, w10, rho_air: float = 1.225, kind: int = 0):
         """A field on its own grid, array [n_times][ny_w][nx_w][2]: wind at

@@ -233,3 +233,9 @@ def test_dt_policy_rejects_null_domain(lib):
 def test_stress_field_rejects_invalid_arguments(lib):
     from paper_1912_02457_amd import swe
     assert lib.swe_set_stress_field(None, 1, 2, 2, None, None, None, 0) == swe.SWE_E_ARG
+
+
+def test_boundary_field_rejects_invalid_arguments(lib):
+    from paper_1912_02457_amd import swe
+    t = (C.c_double * 1)(0.0)
+    assert lib.swe_set_boundary_field(None, 1, 4, 4, t, None) == swe.SWE_E_ARG

@@ -574,6 +574,34 @@ def test_stress_field_uniform_and_interpolated_as_is():
     assert np.abs(rw[1] - ra[1]).max() > 1e-3
 
 
+def test_boundary_field_resampling():
+    """Boundary data at its own spacing (section "Nesting the model": linear
+    interpolation in space): data with one sample per cell comes back
+    unchanged; a profile linear along each side, sampled at the centres of n
+    equal parts, is reproduced exactly at every cell centre inside the first
+    and last sample centre and held beyond them."""
+    nx, ny, n_x, n_y = 40, 25, 7, 4
+    d = np.random.default_rng(3).standard_normal((2, 3, 2 * ny + 2 * nx))
+    assert np.array_equal(O.resample_boundary(d, nx, ny, nx, ny), d)
+    lin = lambda s: 0.3 + 1.7 * s               # position s along a side in [0, 1]
+    xs_y, xs_x = (np.arange(n_y) + 0.5) / n_y, (np.arange(n_x) + 0.5) / n_x
+    side = [lin(xs_y), -lin(xs_y), 2 * lin(xs_x), lin(xs_x) - 1.0]
+    coarse = np.tile(np.concatenate(side), (1, 3, 1))
+    out = O.resample_boundary(coarse, nx, ny, n_x, n_y)[0, 1]
+    cy, cx = (np.arange(ny) + 0.5) / ny, (np.arange(nx) + 0.5) / nx
+    want = [lin(cy), -lin(cy), 2 * lin(cx), lin(cx) - 1.0]
+    clamp = [np.clip(cy, xs_y[0], xs_y[-1]), np.clip(cy, xs_y[0], xs_y[-1]),
+             np.clip(cx, xs_x[0], xs_x[-1]), np.clip(cx, xs_x[0], xs_x[-1])]
+    offs = [0, ny, 2 * ny, 2 * ny + nx]
+    for k, (w, c, o) in enumerate(zip(want, clamp, offs)):
+        m = len(w)
+        sgn = [1.0, -1.0, 2.0, 1.0][k]
+        expect = sgn * lin(c) + (-1.0 if k == 3 else 0.0)
+        np.testing.assert_allclose(out[o:o + m], expect, rtol=0, atol=1e-14)
+        inside = (c == (cy if m == ny else cx))
+        np.testing.assert_allclose(out[o:o + m][inside], w[inside], rtol=0, atol=1e-14)
+
+
 def test_w10_bilinear_in_space_and_linear_in_time():
     """Samples sit at the centres of an nx_w x ny_w partition of the domain
     and are interpolated bilinearly (exact for a field linear in x and y

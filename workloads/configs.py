@@ -67,6 +67,10 @@ class Workload:
     wind_tau: np.ndarray = field(default_factory=lambda: np.zeros((1, 2), np.float32))
     bnd_t: Optional[np.ndarray] = None
     bnd: Optional[np.ndarray] = None
+    # > 0: bnd holds bnd_ny samples along the W/E sides and bnd_nx along S/N
+    # (boundary data at its own spacing); 0: one value per boundary cell
+    bnd_nx: int = 0
+    bnd_ny: int = 0
     # wind at 10 m on its own grid: [n][ny_w][nx_w][2] m/s at times w10_t
     w10_t: Optional[np.ndarray] = None
     w10: Optional[np.ndarray] = None

@@ -68,6 +68,10 @@ def parse():
     ap.add_argument("--serve-max-active", type=int, default=64)
     ap.add_argument("--serve-steps-per-tick", type=int, default=24)
     ap.add_argument("--serve-rows", type=int, default=0, help="rows per tile of the server's ensemble (0 = default)")
+    ap.add_argument("--serve-unloaded-requests", type=int, default=150,
+                    help="requests of the unloaded stream (0 = skip it)")
+    ap.add_argument("--serve-unloaded-spread", type=float, default=8.0,
+                    help="factor on the inter-arrival times of the unloaded stream")
     ap.add_argument("--serve-baseline-requests", type=int, default=60,
                     help="requests of the stream run one by one for the unbatched comparison")
     ap.add_argument("--serve-time-scale", type=float, default=0.1,
@@ -311,20 +315,39 @@ def bench_serving(a, torch):
     f = 1.2e-4, Gaussian bump; sizes 100..2000 x 100..800) arriving as a
     Poisson stream; horizons and inter-arrival times are scaled by
     ``serve_time_scale`` so the offered load matches the full stream's.
-    Latency = completion minus arrival, wall clock."""
+    Latency = completion minus arrival, wall clock.  A second, shorter
+    stream with the arrivals spread out ``serve_unloaded_spread`` times
+    (offered load below what the server sustains) gives the latency of a
+    server that is not queueing."""
+    import numpy as np
+    from workloads import config5_requests
+
+    sc = a.serve_time_scale
+    reqs = config5_requests()[: a.serve_requests]
+    arrivals = np.array([r["arrival"] for r in reqs]) * sc
+    horizons = [r["horizon"] * sc for r in reqs]
+    out = _serve_stream(a, torch, reqs, arrivals, horizons)
+    out["one_by_one"] = serve_one_by_one(reqs[:a.serve_baseline_requests], horizons, torch)
+    if a.serve_unloaded_requests > 0:
+        n = a.serve_unloaded_requests
+        u = _serve_stream(a, torch, reqs[:n], arrivals[:n] * a.serve_unloaded_spread, horizons[:n])
+        out["unloaded"] = {k: u[k] for k in ("workload", "requests", "completed_ok", "latency_s",
+                                             "offered_cell_steps_per_s", "value", "mean_active")}
+    return out
+
+
+def _serve_stream(a, torch, reqs, arrivals, horizons):
+    """One request stream through a fresh server; throughput, latency and
+    server counters."""
     from collections import deque
     from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
 
     from paper_1912_02457_amd import Server
-    from workloads import config5_requests
     from workloads.configs import config5_member
 
     sc = a.serve_time_scale
-    reqs = config5_requests()[: a.serve_requests]
-    arrivals = np.array([r["arrival"] for r in reqs]) * sc
-    horizons = [r["horizon"] * sc for r in reqs]
     srv = Server(48 << 30, max_active=a.serve_max_active, steps_per_tick=a.serve_steps_per_tick,
                  rows_per_wave=a.serve_rows, device="cuda:0")
     done_at = {}
@@ -393,7 +416,8 @@ def bench_serving(a, torch):
         "metric": "served cell-updates/s",
         "value": cell_steps / span,
         "unit": "cell-updates/s",
-        "workload": f"{len(reqs)} forecast requests, Poisson arrivals at {20.0 / sc:.0f}/s, "
+        "workload": f"{len(reqs)} forecast requests, Poisson arrivals at "
+                    f"{(len(reqs) - 1) / max(arrivals[-1] - arrivals[0], 1e-9):.0f}/s, "
                     f"nx 100..2000 x ny 100..800 at 1 km, horizons U[1,24] h x {sc}",
         "requests": len(reqs), "completed_ok": ok, "time_scale": sc,
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
@@ -406,7 +430,6 @@ def bench_serving(a, torch):
         "rows_per_wave": a.serve_rows,
         "arena_peak_GiB": st["arena_peak"] / 2**30,
         "host_s": {k[5:-2]: round(st[k], 3) for k in st if k.startswith("host_")},
-        "one_by_one": serve_one_by_one(reqs[:a.serve_baseline_requests], horizons, torch),
     }
 
 

@@ -109,7 +109,32 @@ def cpu_baseline(wl, target_s):
         "kind": "oracle",
         "sample": f"first {steps} steps of the same {wl.nx}x{wl.ny} workload, FP64 C oracle, "
                   f"{el:.1f} s wall",
-    }
+    }, st, t, steps
+
+
+def error_vs_oracle(wl, ref, t_ref, steps, np):
+    """The HIP path over the oracle sample's steps (its own CFL dt), compared
+    element by element with the FP64 oracle: relative L2 and Linf per field,
+    eta by its own norm, hu and hv by the norm of the momentum magnitude,
+    land cells excluded."""
+    from paper_1912_02457_amd import Domain
+    dom = Domain.from_workload(wl, device="cuda:0")
+    dom.step(steps)
+    e, u, v, t, _ = dom.read_state()
+    dom.close()
+    m = np.ones((wl.ny, wl.nx), bool) if wl.land is None else (np.asarray(wl.land) == 0)
+    re, ru, rv = (np.asarray(x, np.float64)[m] for x in ref)
+    ge, gu, gv = (np.asarray(x, np.float64)[m] for x in (e, u, v))
+    mom = np.sqrt(ru ** 2 + rv ** 2)
+    out = {"steps": steps, "t_s": t, "t_oracle_s": t_ref}
+    for name, g, r, n2, ni in (("eta", ge, re, np.linalg.norm(re), np.abs(re).max()),
+                               ("hu", gu, ru, np.linalg.norm(mom), mom.max()),
+                               ("hv", gv, rv, np.linalg.norm(mom), mom.max())):
+        out[f"{name}_rel_l2"] = float(np.linalg.norm(g - r) / max(n2, 1e-30))
+        out[f"{name}_rel_linf"] = float(np.abs(g - r).max() / max(ni, 1e-30))
+    out["note"] = ("same steps as the cpu_baseline sample; full step counts per configuration: "
+                   "tests/parity_report.py")
+    return out
 
 
 def measured_traffic(kernel: str, rows: int):
@@ -614,8 +639,9 @@ def main():
         out["preprocess"] = bench_preprocess(a, np, torch)
         _progress(f"preprocess: reconstruction {out['preprocess']['reconstruct']['ms_per_call']:.3f} ms")
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds)
+        out["cpu_baseline"], ref, t_ref, steps = cpu_baseline(wl, a.cpu_seconds)
         _progress("cpu baseline done")
+        out["error_vs_oracle"] = error_vs_oracle(wl, ref, t_ref, steps, np)
     print(json.dumps(out), flush=True)
 
 

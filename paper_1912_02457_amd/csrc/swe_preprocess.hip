@@ -84,7 +84,11 @@ __global__ __launch_bounds__(256) void recon_round_kernel(int nx, int ny, int ns
 {
     constexpr int NS = R + 6;  // steps: three warm-up rows below, three above
     const int lane = threadIdx.x & 63;
-    const int item = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    // the wave's index is the same in all its lanes: read it as a scalar, so
+    // that the row offsets below are scalar too and every load and store is
+    // a scalar row base plus the lane's column
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int item = xcd_block(blockIdx.x, gridDim.x) * 4 + wv;
     if (item >= nitems) return;  // whole waves leave together
     const int J0 = (item / nsx) * R, I = (item % nsx) * RSTRIP - 3 + lane;
     const uint32_t Ic = (uint32_t)min(max(I, 0), nx), ic = (uint32_t)min(max(I, 0), nx - 1);
@@ -100,13 +104,15 @@ __global__ __launch_bounds__(256) void recon_round_kernel(int nx, int ny, int ns
     int Lb[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-        Hb[k] = INIT ? 0.f : ldf(Hin, (uint32_t)min(max(a0 + k, 0), ny) * nxc + Ic);
-        Mb[k] = ldf(Hm, (uint32_t)min(max(a0 + k - 1, 0), ny - 1) * (uint32_t)nx + ic);
+        const uint32_t rc = (uint32_t)min(max(a0 + k, 0), ny), rm = (uint32_t)min(max(a0 + k - 1, 0), ny - 1);
+        Hb[k] = INIT ? 0.f : ldf(Hin, rc * nxc + Ic);
+        Mb[k] = ldf(Hm, rm * (uint32_t)nx + ic);
         Lb[k] = 0;
     }
     if (land) {
 #pragma unroll
-        for (int k = 0; k < NS; ++k) Lb[k] = ldb(land, (uint32_t)min(max(a0 + k - 1, 0), ny - 1) * (uint32_t)nx + ic);
+        for (int k = 0; k < NS; ++k)
+            Lb[k] = ldb(land, (uint32_t)min(max(a0 + k - 1, 0), ny - 1) * (uint32_t)nx + ic);
     }
 
     // pipeline registers; names give the row relative to the newest corner row a

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/swe.h: parameter validation,
 // workspace layout, uploads, launches, HIP-graph replay of step chunks and
 // kernel timing.  No exception crosses the ABI.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -762,13 +763,15 @@ int swe_set_tiling(swe_domain *d, int32_t rows_per_wave, int32_t order)
     return SWE_OK;
 }
 
-// Time one stage kernel over candidate tile heights (one warm-up and four
-// event-timed launches each); returns the fastest.
+// Time one stage kernel over candidate tile heights (one warm-up and eight
+// event-timed launches each, compared by their median so that a disturbed
+// launch does not decide); returns the fastest.
 int sweep_stage(swe_domain *d, int stage, int *best_by)
 {
     static const int cand[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 32, 48, 64};
+    constexpr int kReps = 8;
     const bool proj = d->p.north_projection != 0;
-    hipEvent_t ev[8];
+    hipEvent_t ev[2 * kReps];
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     int best = d->T[stage - 1].by;
     float best_ms = INFINITY;
@@ -778,16 +781,17 @@ int sweep_stage(swe_domain *d, int stage, int *best_by)
         Tiling T = make_tiling(d->p.nx, d->p.ny, by);
         if ((he = launch_stage(stage, proj, d->dom, T, d->parity, 0.0, d->stream, nullptr, nullptr)) != hipSuccess)
             break;
-        for (int k = 0; k < 4 && he == hipSuccess; ++k)
+        for (int k = 0; k < kReps && he == hipSuccess; ++k)
             he = launch_stage(stage, proj, d->dom, T, d->parity, 0.0, d->stream, ev[2 * k], ev[2 * k + 1]);
         if (he != hipSuccess || (he = hipStreamSynchronize(d->stream)) != hipSuccess) break;
-        float tot = 0.f;
-        for (int k = 0; k < 4 && he == hipSuccess; ++k) {
-            float ms = 0.f;
-            he = hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]);
-            tot += ms;
+        float ms[kReps];
+        for (int k = 0; k < kReps && he == hipSuccess; ++k) {
+            ms[k] = 0.f;
+            he = hipEventElapsedTime(&ms[k], ev[2 * k], ev[2 * k + 1]);
         }
         if (he != hipSuccess) break;
+        std::sort(ms, ms + kReps);
+        const float tot = ms[kReps / 2 - 1] + ms[kReps / 2];
         if (tot < best_ms * 0.99f) { best_ms = tot; best = by; }
     }
     for (auto &e : ev) (void)hipEventDestroy(e);

@@ -831,7 +831,9 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Ti
                                                                       double dt_fixed)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
+    // the same in every lane of the wave: read as a scalar, so that the tile's
+    // rows and columns, and with them the row offsets, are scalar values
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     // Blocks are dispatched round-robin over the 8 XCDs.  Order bit 1 clear:
     // give each XCD a contiguous range of tiles so neighbouring tiles (which
     // share halo rows) meet in the same L2.  Order bit 0: tiles numbered

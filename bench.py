@@ -81,6 +81,7 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run warmup + this many steps (for rocprofv3 runs), no JSON")
     ap.add_argument("--no-preprocess", action="store_true")
+    ap.add_argument("--no-strip", action="store_true", help="skip the one-strip-of-8 measurement")
     ap.add_argument("--preprocess-only", action="store_true",
                     help="only the device preprocessing section (for profiler runs)")
     ap.add_argument("--preprocess-reps", type=int, default=50)
@@ -266,6 +267,38 @@ def bench_single(a, np, torch):
         "state_finite": finite,
     }
     return out, wl
+
+
+def bench_strip(a, np, torch, wl, full_value):
+    """One GPU's share of the headline domain if it were split into 8 row
+    strips: 2600 x 117 cells (900/8 rows plus the 4 halo rows a stage reads),
+    cut from the same fields, walls on all sides (the exchange with the
+    neighbouring strips is not modelled).  Shows how far below the whole
+    domain's rate a strip runs on its own."""
+    from paper_1912_02457_amd import Domain
+    from workloads import BC_WALL
+    ny = 900 // 8 + 4
+    sw = wl.copy(ny=ny, Hc=wl.Hc[:ny + 1], land=None if wl.land is None else wl.land[:ny], f=wl.f[:ny],
+                 north=None if wl.north is None else wl.north[:ny], eta=wl.eta[:ny], hu=wl.hu[:ny],
+                 hv=wl.hv[:ny], bc=(BC_WALL,) * 4, bnd=None, bnd_t=None)
+    dom = Domain.from_workload(sw, device="cuda:0")
+    dom.autotune()
+    dom.step(100)
+    torch.cuda.synchronize()
+    n = 2000
+    t0 = time.perf_counter()
+    dom.step(n)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    dom.enable_timing(True)
+    dom.stage_times(reset=True)
+    dom.step(500)
+    ms1, ms2, _ = dom.stage_times(reset=True)
+    dom.close()
+    v = sw.nx * sw.ny * n / el
+    return {"shape": [sw.nx, sw.ny], "value": v, "unit": "cell-updates/s", "ms_per_step": el / n * 1e3,
+            "stage1_ms": ms1, "stage2_ms": ms2, "rate_vs_whole_domain": v / full_value,
+            "note": "one of 8 row strips of the headline domain with its halo rows, walls, no exchange"}
 
 
 def _member(k):
@@ -631,6 +664,9 @@ def main():
     if out is None:
         return
     _progress(f"single domain: {out['value']:.3e} cell-updates/s")
+    if not a.no_strip:
+        out["strip_of_8"] = bench_strip(a, np, torch, wl, out["value"])
+        _progress(f"strip: {out['strip_of_8']['value']:.3e} cell-updates/s")
     if not a.no_ensemble:
         out["ensemble"] = bench_ensemble(a, torch)
         _progress(f"ensemble: {out['ensemble']['value']:.3e} cell-updates/s")

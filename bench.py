@@ -46,11 +46,12 @@ BYTES = {1: (32, 20), 2: (44, 20)}
 # this build; a quarter-rate transcendental -- rcp, sqrt, exp, log -- takes 4
 # slots).  Per-cell work of each stage kernel = the VALU slots of one row step
 # of its interior tile loop, one lane per cell (gfx950 assembly of
-# swe_kernels.hip: the row's main block and the blocks every row runs, plus a
-# share of the loop's per-iteration blocks, averaged over the unrolled rows;
-# linear friction): no halo lane, halo row, boundary or tail overhead counted.
+# swe_kernels.hip: the blocks a row runs with linear friction -- the blocks of
+# the other friction laws sit behind a uniform branch and are left out --
+# plus a share of the loop's per-iteration blocks, averaged over the unrolled
+# rows): no halo lane, halo row, boundary or tail overhead counted.
 VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
-VALU_SLOTS_PER_CELL = {1: 374 + 3 * 12, 2: 409 + 3 * 14}
+VALU_SLOTS_PER_CELL = {1: 362 + 3 * 12, 2: 397 + 3 * 14}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_kernels_norkyst_2600x900.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1912_02457_amd", "csrc", "swe_kernels.hip")
 

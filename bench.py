@@ -83,6 +83,10 @@ def parse():
                     help="only run warmup + this many steps (for rocprofv3 runs), no JSON")
     ap.add_argument("--no-preprocess", action="store_true")
     ap.add_argument("--no-strip", action="store_true", help="skip the one-strip-of-8 measurement")
+    ap.add_argument("--no-compensated", action="store_true",
+                    help="skip the measurement of the compensated-state variant")
+    ap.add_argument("--compensated", action="store_true",
+                    help="with --profile-steps: profile the compensated-state kernels instead")
     ap.add_argument("--preprocess-only", action="store_true",
                     help="only the device preprocessing section (for profiler runs)")
     ap.add_argument("--preprocess-reps", type=int, default=50)
@@ -116,13 +120,13 @@ def cpu_baseline(wl, target_s):
     }, st, t, steps
 
 
-def error_vs_oracle(wl, ref, t_ref, steps, np):
+def error_vs_oracle(wl, ref, t_ref, steps, np, compensated=False):
     """The HIP path over the oracle sample's steps (its own CFL dt), compared
     element by element with the FP64 oracle: relative L2 and Linf per field,
     eta by its own norm, hu and hv by the norm of the momentum magnitude,
     land cells excluded."""
     from paper_1912_02457_amd import Domain
-    dom = Domain.from_workload(wl, device="cuda:0")
+    dom = Domain.from_workload(wl, device="cuda:0", compensated_state=compensated)
     dom.step(steps)
     e, u, v, t, _ = dom.read_state()
     dom.close()
@@ -168,7 +172,7 @@ def bench_single(a, np, torch):
     cells = wl.nx * wl.ny
     land_cells = int(np.count_nonzero(wl.land)) if wl.land is not None else 0
     wet_cells = cells - land_cells
-    dom = Domain.from_workload(wl, device="cuda:0")
+    dom = Domain.from_workload(wl, device="cuda:0", compensated_state=a.compensated and a.profile_steps > 0)
     dom.autotune()  # measured tile height (does not advance the simulation)
     rows_per_wave, tile_order, waves = dom.tiling(1)
     rows2, _, waves2 = dom.tiling(2)
@@ -300,6 +304,31 @@ def bench_strip(a, np, torch, wl, full_value):
     return {"shape": [sw.nx, sw.ny], "value": v, "unit": "cell-updates/s", "ms_per_step": el / n * 1e3,
             "stage1_ms": ms1, "stage2_ms": ms2, "rate_vs_whole_domain": v / full_value,
             "note": "one of 8 row strips of the headline domain with its halo rows, walls, no exchange"}
+
+
+def bench_compensated(a, np, torch, wl, full_value):
+    """The headline workload with the compensated state (each stored value of
+    the state keeps its float32 rounding error in a second plane): the price
+    of taking state rounding out of the error over long runs."""
+    from paper_1912_02457_amd import Domain
+    dom = Domain.from_workload(wl, device="cuda:0", compensated_state=True)
+    dom.autotune()
+    dom.step(a.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dom.step(a.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    dom.enable_timing(True)
+    dom.stage_times(reset=True)
+    dom.step(min(a.steps, 1000))
+    ms1, ms2, _ = dom.stage_times(reset=True)
+    rows = [dom.tiling(1)[0], dom.tiling(2)[0]]
+    dom.close()
+    v = wl.nx * wl.ny * a.steps / el
+    return {"value": v, "unit": "cell-updates/s", "ms_per_step": el / a.steps * 1e3, "steps": a.steps,
+            "stage1_ms": ms1, "stage2_ms": ms2, "rows_per_wave": rows, "rate_vs_float32_state": v / full_value,
+            "note": "same workload and timed region as the headline, compensated_state=1"}
 
 
 def _member(k):
@@ -668,6 +697,9 @@ def main():
     if not a.no_strip:
         out["strip_of_8"] = bench_strip(a, np, torch, wl, out["value"])
         _progress(f"strip: {out['strip_of_8']['value']:.3e} cell-updates/s")
+    if not a.no_compensated:
+        out["compensated_state"] = bench_compensated(a, np, torch, wl, out["value"])
+        _progress(f"compensated: {out['compensated_state']['value']:.3e} cell-updates/s")
     if not a.no_ensemble:
         out["ensemble"] = bench_ensemble(a, torch)
         _progress(f"ensemble: {out['ensemble']['value']:.3e} cell-updates/s")
@@ -681,6 +713,7 @@ def main():
         out["cpu_baseline"], ref, t_ref, steps = cpu_baseline(wl, a.cpu_seconds)
         _progress("cpu baseline done")
         out["error_vs_oracle"] = error_vs_oracle(wl, ref, t_ref, steps, np)
+        out["error_vs_oracle_compensated"] = error_vs_oracle(wl, ref, t_ref, steps, np, compensated=True)
     print(json.dumps(out), flush=True)
 
 

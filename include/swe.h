@@ -73,6 +73,13 @@ typedef struct swe_params {
     int32_t north_projection;/* 0: Coriolis as f (hv, -hu); 1: evaluate the north-vector
                                 projection of the section "Coriolis force" literally
                                 (reads the north angle every stage) */
+    int32_t compensated_state;/* 0: the state is stored in float32, as in the paper;
+                                1: each stored value of Q^n and Q* also keeps its
+                                rounding error (a second float32 plane per field),
+                                updated by an error-free sum, so that storing the
+                                state rounds away nothing across steps; the
+                                arithmetic of a stage stays float32.  Six more
+                                planes of workspace. */
 } swe_params;
 
 typedef struct swe_domain swe_domain;

@@ -50,6 +50,9 @@ Layout make_layout(const swe_params &p, int max_wind, int max_bnd)
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, kAlign); return o; };
     L.eta = take(plane); L.hu = take(plane); L.hv = take(plane);
     L.eta1 = take(plane); L.hu1 = take(plane); L.hv1 = take(plane);
+    const size_t lo = p.compensated_state ? plane : 0;
+    L.eta_lo = take(lo); L.hu_lo = take(lo); L.hv_lo = take(lo);
+    L.eta1_lo = take(lo); L.hu1_lo = take(lo); L.hv1_lo = take(lo);
     L.Hc = take(cplane);
     L.f = take(plane);
     L.north = p.north_projection ? take(plane) : take(0);
@@ -94,6 +97,8 @@ int validate(const swe_params *p)
     if (p->frs_width < 1 || p->frs_width > kMaxFrs) return fail(SWE_E_ARG, "frs_width must be in [1, 32]");
     if (!(std::isfinite(p->frs_d0) && p->frs_d0 > 0)) return fail(SWE_E_ARG, "frs_d0 must be > 0");
     if (p->north_projection != 0 && p->north_projection != 1) return fail(SWE_E_ARG, "north_projection must be 0 or 1");
+    if (p->compensated_state != 0 && p->compensated_state != 1)
+        return fail(SWE_E_ARG, "compensated_state must be 0 or 1");
     return SWE_OK;
 }
 
@@ -225,6 +230,10 @@ int copy_state_to_star(swe_domain *d)
     HIP_TRY(hipMemcpyAsync(d->dom.eta1, d->dom.eta, plane, hipMemcpyDeviceToDevice, d->stream));
     HIP_TRY(hipMemcpyAsync(d->dom.hu1, d->dom.hu, plane, hipMemcpyDeviceToDevice, d->stream));
     HIP_TRY(hipMemcpyAsync(d->dom.hv1, d->dom.hv, plane, hipMemcpyDeviceToDevice, d->stream));
+    // a state handed in as float32 values carries no rounding error yet
+    float *lo[6] = {d->dom.eta_lo, d->dom.hu_lo, d->dom.hv_lo, d->dom.eta1_lo, d->dom.hu1_lo, d->dom.hv1_lo};
+    for (float *q : lo)
+        if (q) HIP_TRY(hipMemsetAsync(q, 0, plane, d->stream));
     return SWE_OK;
 }
 
@@ -296,6 +305,16 @@ int read_ctrl(swe_domain *d, Ctrl *c)
     HIP_TRY(hipMemcpyAsync(d->pinned_ctrl, d->dom.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, d->stream));
     HIP_TRY(hipStreamSynchronize(d->stream));
     std::memcpy(c, d->pinned_ctrl, sizeof(Ctrl));
+    return SWE_OK;
+}
+
+// Pinned host planes for state copies: three (eta, hu, hv), and three more
+// for their rounding errors when the state is compensated.
+int ensure_pinned_state(swe_domain *d)
+{
+    if (d->pinned_state) return SWE_OK;
+    const size_t n = (size_t)(d->p.compensated_state ? 6 : 3) * d->p.nx * d->p.ny;
+    HIP_TRY(hipHostMalloc((void **)&d->pinned_state, n * sizeof(float), hipHostMallocDefault));
     return SWE_OK;
 }
 
@@ -385,6 +404,10 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
     char *w = d->ws;
     D.eta = (float *)(w + L.eta); D.hu = (float *)(w + L.hu); D.hv = (float *)(w + L.hv);
     D.eta1 = (float *)(w + L.eta1); D.hu1 = (float *)(w + L.hu1); D.hv1 = (float *)(w + L.hv1);
+    if (p->compensated_state) {
+        D.eta_lo = (float *)(w + L.eta_lo); D.hu_lo = (float *)(w + L.hu_lo); D.hv_lo = (float *)(w + L.hv_lo);
+        D.eta1_lo = (float *)(w + L.eta1_lo); D.hu1_lo = (float *)(w + L.hu1_lo); D.hv1_lo = (float *)(w + L.hv1_lo);
+    }
     D.Hc = (const float *)(w + L.Hc);
     D.f = (const float *)(w + L.f);
     D.north = p->north_projection ? (const float *)(w + L.north) : nullptr;
@@ -401,7 +424,7 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
         d->cus = cus > 0 ? cus : 256;
     }
     for (int st = 0; st < 2; ++st) {
-        d->wps[st] = stage_waves_per_simd(st + 1, p->north_projection != 0);
+        d->wps[st] = stage_waves_per_simd(st + 1, p->north_projection != 0, p->compensated_state != 0);
         d->T[st] = make_tiling(nx, ny, pick_rows_per_wave(nx, ny, d->cus, d->wps[st]));
     }
 
@@ -673,8 +696,8 @@ int swe_read_state(swe_domain *d, float *eta, float *hu, float *hv, double *t, d
         if (!dst[k]) continue;
         float *to = dst[k];
         if (is_pageable(dst[k])) {
-            if (!d->pinned_state)
-                HIP_TRY(hipHostMalloc((void **)&d->pinned_state, 3 * plane * sizeof(float), hipHostMallocDefault));
+            int rc0 = ensure_pinned_state(d);
+            if (rc0) return rc0;
             to = d->pinned_state + k * plane;
             staged[k] = true;
         }
@@ -805,16 +828,17 @@ int swe_autotune_tiling(swe_domain *d, int32_t *rows_per_wave)
     int rc = check_ready(d);
     if (rc) return rc;
     // Stage 1 writes only Q*, which every step overwrites; stage 2 writes
-    // Q^{n+1} over Q^n.  Q^n and the control block (time, step count, CFL
-    // slots) are saved first and put back afterwards, so the sweep leaves the
-    // simulation where it was.
+    // Q^{n+1} over Q^n.  Q^n (with its rounding errors when compensated) and
+    // the control block (time, step count, CFL slots) are saved first and put
+    // back afterwards, so the sweep leaves the simulation where it was.
     Ctrl saved;
     if ((rc = read_ctrl(d, &saved))) return rc;
     const int nx = d->p.nx, ny = d->p.ny;
     const size_t plane = (size_t)nx * ny, row = (size_t)nx * sizeof(float), dp = (size_t)d->dom.pitch * sizeof(float);
-    if (!d->pinned_state) HIP_TRY(hipHostMalloc((void **)&d->pinned_state, 3 * plane * sizeof(float), hipHostMallocDefault));
-    float *q[3] = {d->dom.eta, d->dom.hu, d->dom.hv};
-    for (int k = 0; k < 3; ++k)
+    if ((rc = ensure_pinned_state(d))) return rc;
+    float *q[6] = {d->dom.eta, d->dom.hu, d->dom.hv, d->dom.eta_lo, d->dom.hu_lo, d->dom.hv_lo};
+    const int nq = d->p.compensated_state ? 6 : 3;
+    for (int k = 0; k < nq; ++k)
         HIP_TRY(hipMemcpy2DAsync(d->pinned_state + k * plane, row, q[k], dp, row, ny, hipMemcpyDeviceToHost, d->stream));
     int by1 = 0, by2 = 0;
     rc = sweep_stage(d, 1, &by1);
@@ -824,7 +848,7 @@ int swe_autotune_tiling(swe_domain *d, int32_t *rows_per_wave)
         rc = e != hipSuccess ? hip_fail(e, "launch_stage") : sweep_stage(d, 2, &by2);
     }
     // the state and control block go back even when the sweep failed
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < nq; ++k)
         HIP_TRY(hipMemcpy2DAsync(q[k], dp, d->pinned_state + k * plane, row, row, ny, hipMemcpyHostToDevice, d->stream));
     HIP_TRY(hipMemcpyAsync(d->dom.ctrl, &saved, sizeof(Ctrl), hipMemcpyHostToDevice, d->stream));
     HIP_TRY(hipStreamSynchronize(d->stream));

@@ -73,6 +73,7 @@ struct swe_ensemble {
     int parity = 0;
     bool proj = false;
     bool w10 = false;  // some member has a gridded wind field
+    bool comp = false; // members keep a compensated state
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_objs;
     bool timing = false;
@@ -101,14 +102,14 @@ int launch_ens_step(swe_ensemble *e, int parity, hipStream_t s, bool timed)
             e->ev_pool.push_back(ev);
         }
         hipEvent_t *pe = &e->ev_pool[e->ev_used];
-        EHIP(launch_ensemble(1, e->proj, e->w10, e->d_mem, e->d_items, e->d_ctrl, parity, e->chunk, e->nblocks, s, pe[0], pe[1]));
-        EHIP(launch_ensemble(2, e->proj, e->w10, e->d_mem, e->d_items, e->d_ctrl, parity, e->chunk, e->nblocks, s, pe[2], pe[3]));
+        EHIP(launch_ensemble(1, e->proj, e->w10, e->comp, e->d_mem, e->d_items, e->d_ctrl, parity, e->chunk, e->nblocks, s, pe[0], pe[1]));
+        EHIP(launch_ensemble(2, e->proj, e->w10, e->comp, e->d_mem, e->d_items, e->d_ctrl, parity, e->chunk, e->nblocks, s, pe[2], pe[3]));
         e->ev_used += 4;
         e->timed_steps += 1;
         return SWE_OK;
     }
-    EHIP(launch_ensemble(1, e->proj, e->w10, e->d_mem, e->d_items, e->d_ctrl, parity, e->chunk, e->nblocks, s, nullptr, nullptr));
-    EHIP(launch_ensemble(2, e->proj, e->w10, e->d_mem, e->d_items, e->d_ctrl, parity, e->chunk, e->nblocks, s, nullptr, nullptr));
+    EHIP(launch_ensemble(1, e->proj, e->w10, e->comp, e->d_mem, e->d_items, e->d_ctrl, parity, e->chunk, e->nblocks, s, nullptr, nullptr));
+    EHIP(launch_ensemble(2, e->proj, e->w10, e->comp, e->d_mem, e->d_items, e->d_ctrl, parity, e->chunk, e->nblocks, s, nullptr, nullptr));
     return SWE_OK;
 }
 
@@ -144,6 +145,8 @@ int check_members(swe_domain *const *m, int n)
             if (m[j] == m[k]) return set_error(SWE_E_ARG, "member listed twice");
         if (m[k]->p.north_projection != m[0]->p.north_projection)
             return set_error(SWE_E_ARG, "members must share north_projection");
+        if (m[k]->p.compensated_state != m[0]->p.compensated_state)
+            return set_error(SWE_E_ARG, "members must share compensated_state");
         bool nested = false;
         for (int s = 0; s < 4; ++s) nested |= m[k]->p.bc[s] == SWE_BC_NESTED;
         if (nested && !m[k]->has_bnd) return set_error(SWE_E_STATE, "nested member without boundary data");
@@ -193,8 +196,9 @@ int swe_ensemble_create(swe_domain *const *members, int32_t n, void *dev_workspa
     e->by = by;
     e->chunk = chunk ? chunk : kDefaultChunk;
     e->proj = members[0]->p.north_projection != 0;
+    e->comp = members[0]->p.compensated_state != 0;
     for (int k = 0; k < n; ++k) e->w10 |= members[k]->dom.w10n > 0;
-    int w1 = ensemble_waves_per_simd(1, e->proj), w2 = ensemble_waves_per_simd(2, e->proj);
+    int w1 = ensemble_waves_per_simd(1, e->proj, e->comp), w2 = ensemble_waves_per_simd(2, e->proj, e->comp);
     e->nblocks = members[0]->cus * std::min(w1, w2);  // one wave per SIMD per block
     e->nblocks = (e->nblocks + kEnsParts - 1) / kEnsParts * kEnsParts;
 

@@ -14,15 +14,16 @@
 namespace swe {
 hipError_t launch_stage(int stage, bool proj, const Dom &d, const Tiling &T, int parity, double dt_fixed,
                         hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
-hipError_t launch_ensemble(int stage, bool proj, bool w10, const EnsMember *mem, const EnsItem *items, EnsCtrl *ec,
-                           int parity, int chunk, int nblocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_ensemble(int stage, bool proj, bool w10, bool comp, const EnsMember *mem, const EnsItem *items,
+                           EnsCtrl *ec, int parity, int chunk, int nblocks, hipStream_t s, hipEvent_t ev0,
+                           hipEvent_t ev1);
 hipError_t launch_cfl(const Dom &d, int slot, hipStream_t s);
 hipError_t launch_ctrl_reset(Ctrl *c, double t, int slot, hipStream_t s);
 hipError_t launch_set_t_end(Ctrl *c, double te, hipStream_t s);
 hipError_t launch_policy_reset(Ctrl *c, int parity, hipStream_t s);
 hipError_t launch_diagnostics(const Dom &d, hipStream_t s);
-int stage_waves_per_simd(int stage, bool proj);
-int ensemble_waves_per_simd(int stage, bool proj);
+int stage_waves_per_simd(int stage, bool proj, bool comp);
+int ensemble_waves_per_simd(int stage, bool proj, bool comp);
 
 int set_error(int code, const std::string &msg);  // records the message for swe_last_error
 // A member destroyed while it still belongs to an ensemble: the ensemble
@@ -32,8 +33,8 @@ void ensemble_forget(swe_ensemble *e, swe_domain *d);
 size_t ensemble_bytes_for_shapes(const std::vector<std::pair<int, int>> &shapes, int rows_per_wave);
 
 struct Layout {
-    size_t eta, hu, hv, eta1, hu1, hv1, Hc, f, north, fghost, nghost, alpha, bnd_t, bnd, wind_t, wind,
-        ctrl, partials, total;
+    size_t eta, hu, hv, eta1, hu1, hv1, eta_lo, hu_lo, hv_lo, eta1_lo, hu1_lo, hv1_lo, Hc, f, north, fghost,
+        nghost, alpha, bnd_t, bnd, wind_t, wind, ctrl, partials, total;
 };
 
 }  // namespace swe

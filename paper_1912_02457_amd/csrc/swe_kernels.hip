@@ -49,6 +49,19 @@ __device__ __forceinline__ void st(float *__restrict__ base, uint32_t off, float
 }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// a + b = s + err exactly (Knuth's TwoSum, no assumption on the magnitudes)
+__device__ __forceinline__ float two_sum(float a, float b, float &err)
+{
+    const float s = a + b, bp = s - a, ap = s - bp;
+    err = (a - ap) + (b - bp);
+    return s;
+}
+
+// rounding errors of the own cell's stored Q^n (0) and Q* (1) values
+struct Lo {
+    float e0, u0, v0, e1, u1, v1;
+};
+
 // Value held by lane-1 / lane+1 through a whole-wave DPP shift (wave_shr:1
 // and wave_shl:1 of the GFX9 DPP controls; a VALU operand modifier, no LDS
 // round trip).  Lane 0 / lane 63 receive 0; they are halo lanes whose results
@@ -430,10 +443,10 @@ __device__ __forceinline__ FrsPre frs_prefetch(const Dom &d, const TileCtx &c)
 // x-direction reconstruction and flux of the output row A, the update of
 // eq. rk2_semiimp and (stage 2) the flow relaxation and CFL reduction.
 // Every lane takes part in the cross-lane exchanges; only output lanes store.
-template <int STAGE, bool PROJ, bool FRS, bool W10>
+template <int STAGE, bool PROJ, bool FRS, bool W10, bool COMP>
 __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 &Gn, const TileCtx &c,
-                                           float e0, float u0, float v0, const FrsPre &fp, const Dom &d,
-                                           float &wmax_loc, int &bad)
+                                           float e0, float u0, float v0, const Lo &lo, const FrsPre &fp,
+                                           const Dom &d, float &wmax_loc, int &bad)
 {
     const float th = d.theta;
     float eL = from_left(A.e), cxL = from_left(A.cx);
@@ -486,33 +499,73 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
     float S = friction_coeff(d, A.ri, A.u, A.v);
     if (STAGE == 1) {
         float den = rcp(1.f + dt * S);
-        float en = A.e + dt * Me;
-        float un = (A.u + dt * Mu) * den;
-        float vn = (A.v + dt * Mv) * den;
-        if (store) {
-            st(d.eta1, oo, en);
-            st(d.hu1, oo, un);
-            st(d.hv1, oo, vn);
+        if (COMP) {
+            // compensated: the increment of each field, added to the stored
+            // value plus its rounding error without losing the new error
+            float le, lu, lv;
+            const float en = two_sum(A.e, dt * Me + lo.e0, le);
+            const float un = two_sum(A.u, (dt * Mu - dt * S * A.u) * den + lo.u0, lu);
+            const float vn = two_sum(A.v, (dt * Mv - dt * S * A.v) * den + lo.v0, lv);
+            if (store) {
+                st(d.eta1, oo, en);
+                st(d.hu1, oo, un);
+                st(d.hv1, oo, vn);
+                st(d.eta1_lo, oo, le);
+                st(d.hu1_lo, oo, lu);
+                st(d.hv1_lo, oo, lv);
+            }
+        } else {
+            float en = A.e + dt * Me;
+            float un = (A.u + dt * Mu) * den;
+            float vn = (A.v + dt * Mv) * den;
+            if (store) {
+                st(d.eta1, oo, en);
+                st(d.hu1, oo, un);
+                st(d.hv1, oo, vn);
+            }
         }
     } else {
         float den = rcp(1.f + 0.5f * dt * S);
-        float en = 0.5f * (e0 + (A.e + dt * Me));
-        float un = 0.5f * (u0 + (A.u + dt * Mu)) * den;
-        float vn = 0.5f * (v0 + (A.v + dt * Mv)) * den;
+        float en, un, vn, le = 0.f, lu = 0.f, lv = 0.f;
+        if (COMP) {
+            // Q^{n+1} = Q^n + (Q* - Q^n + dt M(Q*))/2 (momenta with the
+            // friction factor), the differences taken with both errors
+            const float de = (A.e - e0) + (lo.e1 - lo.e0);
+            const float du = (A.u - u0) + (lo.u1 - lo.u0);
+            const float dv = (A.v - v0) + (lo.v1 - lo.v0);
+            en = two_sum(e0, 0.5f * (de + dt * Me) + lo.e0, le);
+            un = two_sum(u0, (0.5f * (du + dt * Mu) - 0.5f * dt * S * u0) * den + lo.u0, lu);
+            vn = two_sum(v0, (0.5f * (dv + dt * Mv) - 0.5f * dt * S * v0) * den + lo.v0, lv);
+        } else {
+            en = 0.5f * (e0 + (A.e + dt * Me));
+            un = 0.5f * (u0 + (A.u + dt * Mu)) * den;
+            vn = 0.5f * (v0 + (A.v + dt * Mv)) * den;
+        }
         if (FRS && fp.zone) {
             const float al = fp.al;
             const double t = c.bs;
             float ex[3];
 #pragma unroll
             for (int q = 0; q < 3; ++q) ex[q] = (float)((1.0 - t) * (double)fp.a[q] + t * (double)fp.b[q]);
-            en = (1.f - al) * en + al * ex[0];
-            un = (1.f - al) * un + al * ex[1];
-            vn = (1.f - al) * vn + al * ex[2];
+            if (COMP) {
+                en = two_sum(en, le + al * ((ex[0] - en) - le), le);
+                un = two_sum(un, lu + al * ((ex[1] - un) - lu), lu);
+                vn = two_sum(vn, lv + al * ((ex[2] - vn) - lv), lv);
+            } else {
+                en = (1.f - al) * en + al * ex[0];
+                un = (1.f - al) * un + al * ex[1];
+                vn = (1.f - al) * vn + al * ex[2];
+            }
         }
         if (store) {
             st(d.eta, oo, en);
             st(d.hu, oo, un);
             st(d.hv, oo, vn);
+            if (COMP) {
+                st(d.eta_lo, oo, le);
+                st(d.hu_lo, oo, lu);
+                st(d.hv_lo, oo, lv);
+            }
         }
         // eq. cfl on the new state
         float h = en + A.Hb;
@@ -600,7 +653,7 @@ __device__ __forceinline__ RawRow load_row(const Dom &d, const float *__restrict
     return w;
 }
 
-template <int STAGE, bool PROJ, bool GHOST, bool FRS, bool W10>
+template <int STAGE, bool PROJ, bool GHOST, bool FRS, bool W10, bool COMP>
 __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1, float &wmax_loc, int &bad)
 {
     const float *__restrict__ E = STAGE == 1 ? d.eta : d.eta1;
@@ -666,11 +719,23 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
     auto step = [&](Row &A, Row &B, Row &C, int k) {
         c.o = k - 2;
         float e0 = 0.f, u0 = 0.f, v0 = 0.f;
+        Lo lo{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (STAGE == 2 && (!GHOST || c.out_lane)) {
             const uint32_t oq = (uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i;
             e0 = ld(d.eta, oq);
             u0 = ld(d.hu, oq);
             v0 = ld(d.hv, oq);
+        }
+        if (COMP && (!GHOST || c.out_lane)) {
+            const uint32_t oq = (uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i;
+            lo.e0 = ld(d.eta_lo, oq);
+            lo.u0 = ld(d.hu_lo, oq);
+            lo.v0 = ld(d.hv_lo, oq);
+            if (STAGE == 2) {
+                lo.e1 = ld(d.eta1_lo, oq);
+                lo.u1 = ld(d.hu1_lo, oq);
+                lo.v1 = ld(d.hv1_lo, oq);
+            }
         }
         FrsPre fp;
         fp.zone = false;
@@ -682,7 +747,7 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
         F3 Gn = y_flux(A, B, us, vs, d);
         // a row whose output cells are all land has nothing to update
         if (__ballot(c.out_lane && !A.land) != 0)
-            finish_row<STAGE, PROJ, FRS, W10>(A, Gs, Gn, c, e0, u0, v0, fp, d, wmax_loc, bad);
+            finish_row<STAGE, PROJ, FRS, W10, COMP>(A, Gs, Gn, c, e0, u0, v0, lo, fp, d, wmax_loc, bad);
         Gs = Gn;
     };
     for (int k = y0 + 2;;) {
@@ -765,7 +830,7 @@ __device__ __forceinline__ void advance_ctrl(Ctrl *ctrl, const StepTime &s, int 
 //            then flow relaxation (eq. frs) and the CFL reduction for the
 //            next step (eq. cfl)
 // eq. rk2_semiimp; M is eq. sw_semidiscrete with the sources of eq. swe.
-template <int STAGE, bool PROJ, bool W10>
+template <int STAGE, bool PROJ, bool W10, bool COMP>
 __device__ __forceinline__ void process_tile(const Dom &d, const Tiling &T, int tile, int parity, const StepTime &st,
                                              int lane)
 {
@@ -808,10 +873,10 @@ __device__ __forceinline__ void process_tile(const Dom &d, const Tiling &T, int 
     }
     float wmax_loc = 0.f;
     int bad = 0;
-    if (!ghost && !frs) run_tile<STAGE, PROJ, false, false, W10>(d, c, y0, y1, wmax_loc, bad);
-    else if (!ghost) run_tile<STAGE, PROJ, false, true, W10>(d, c, y0, y1, wmax_loc, bad);
-    else if (!frs) run_tile<STAGE, PROJ, true, false, W10>(d, c, y0, y1, wmax_loc, bad);
-    else run_tile<STAGE, PROJ, true, true, W10>(d, c, y0, y1, wmax_loc, bad);
+    if (!ghost && !frs) run_tile<STAGE, PROJ, false, false, W10, COMP>(d, c, y0, y1, wmax_loc, bad);
+    else if (!ghost) run_tile<STAGE, PROJ, false, true, W10, COMP>(d, c, y0, y1, wmax_loc, bad);
+    else if (!frs) run_tile<STAGE, PROJ, true, false, W10, COMP>(d, c, y0, y1, wmax_loc, bad);
+    else run_tile<STAGE, PROJ, true, true, W10, COMP>(d, c, y0, y1, wmax_loc, bad);
 
     if (STAGE == 2) {
         wmax_loc = wave_max(wmax_loc);
@@ -826,7 +891,7 @@ __device__ __forceinline__ void process_tile(const Dom &d, const Tiling &T, int 
 // ---------------------------------------------------------------------------
 // single-domain stage kernel: one wavefront per tile
 // ---------------------------------------------------------------------------
-template <int STAGE, bool PROJ, bool W10>
+template <int STAGE, bool PROJ, bool W10, bool COMP>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Tiling T, int parity,
                                                                       double dt_fixed)
 {
@@ -846,7 +911,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Ti
     const StepTime st = step_time(d, parity, dt_fixed, lane);
     if (STAGE == 1 && b == 0 && wid == 0) advance_ctrl(d.ctrl, st, parity, lane);
     if (st.skip || tile >= T.ntiles) return;
-    process_tile<STAGE, PROJ, W10>(d, T, tile, parity, st, lane);
+    process_tile<STAGE, PROJ, W10, COMP>(d, T, tile, parity, st, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -856,7 +921,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Ti
 // chunks taken with one atomicAdd each, until the partition is exhausted.
 // Every member has its own parameters, time, dt slot and CFL accumulator.
 // ---------------------------------------------------------------------------
-template <int STAGE, bool PROJ, bool W10>
+template <int STAGE, bool PROJ, bool W10, bool COMP>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) void ensemble_kernel(const EnsMember *__restrict__ mem,
                                                                          const EnsItem *__restrict__ items,
                                                                          EnsCtrl *ec, int parity, int chunk)
@@ -884,7 +949,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void ensemble_kernel(const 
             const int p = parity ^ M.pflip;
             const StepTime st = step_time(M.d, p, 0.0, lane);
             if (STAGE == 1 && it.tile == 0) advance_ctrl(M.d.ctrl, st, p, lane);
-            if (!st.skip) process_tile<STAGE, PROJ, W10>(M.d, M.T, it.tile, p, st, lane);
+            if (!st.skip) process_tile<STAGE, PROJ, W10, COMP>(M.d, M.T, it.tile, p, st, lane);
         }
     }
 }
@@ -1021,88 +1086,101 @@ __global__ __launch_bounds__(kDiagThreads) void diag_final_kernel(Dom d)
 // ---------------------------------------------------------------------------
 // launch wrappers (host side)
 // ---------------------------------------------------------------------------
-// Kernel variants: stage (1, 2) x literal north projection x gridded wind.
-// The wind-field code is compiled only into the W10 variants (it would
-// otherwise raise the register count of every launch).
-template <int S, bool P, bool W>
+// Kernel variants: stage (1, 2) x literal north projection x gridded wind x
+// compensated state.  The wind-field and compensated-state code is compiled
+// only into their own variants (it would otherwise raise the register count
+// of every launch).
+template <int S, bool P, bool W, bool C>
 hipError_t launch_stage_v(const Dom &d, const Tiling &T, int parity, double dt_fixed, hipStream_t s, hipEvent_t ev0,
                           hipEvent_t ev1)
 {
     dim3 grid(T.nblocks), block(kWave * kWavesPerBlock);
-    if (ev0) hipExtLaunchKernelGGL(stage_kernel<S, P, W>, grid, block, 0, s, ev0, ev1, 0, d, T, parity, dt_fixed);
-    else stage_kernel<S, P, W><<<grid, block, 0, s>>>(d, T, parity, dt_fixed);
+    if (ev0) hipExtLaunchKernelGGL(stage_kernel<S, P, W, C>, grid, block, 0, s, ev0, ev1, 0, d, T, parity, dt_fixed);
+    else stage_kernel<S, P, W, C><<<grid, block, 0, s>>>(d, T, parity, dt_fixed);
     return hipGetLastError();
+}
+
+template <int S, bool P>
+hipError_t launch_stage_pc(bool w, bool c, const Dom &d, const Tiling &T, int parity, double dt_fixed,
+                           hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (c) return w ? launch_stage_v<S, P, true, true>(d, T, parity, dt_fixed, s, ev0, ev1)
+                    : launch_stage_v<S, P, false, true>(d, T, parity, dt_fixed, s, ev0, ev1);
+    return w ? launch_stage_v<S, P, true, false>(d, T, parity, dt_fixed, s, ev0, ev1)
+             : launch_stage_v<S, P, false, false>(d, T, parity, dt_fixed, s, ev0, ev1);
 }
 
 hipError_t launch_stage(int stage, bool proj, const Dom &d, const Tiling &T, int parity, double dt_fixed,
                         hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    const bool w = d.w10n > 0;
-    switch ((stage == 2 ? 4 : 0) | (proj ? 2 : 0) | (w ? 1 : 0)) {
-    case 0: return launch_stage_v<1, false, false>(d, T, parity, dt_fixed, s, ev0, ev1);
-    case 1: return launch_stage_v<1, false, true>(d, T, parity, dt_fixed, s, ev0, ev1);
-    case 2: return launch_stage_v<1, true, false>(d, T, parity, dt_fixed, s, ev0, ev1);
-    case 3: return launch_stage_v<1, true, true>(d, T, parity, dt_fixed, s, ev0, ev1);
-    case 4: return launch_stage_v<2, false, false>(d, T, parity, dt_fixed, s, ev0, ev1);
-    case 5: return launch_stage_v<2, false, true>(d, T, parity, dt_fixed, s, ev0, ev1);
-    case 6: return launch_stage_v<2, true, false>(d, T, parity, dt_fixed, s, ev0, ev1);
-    default: return launch_stage_v<2, true, true>(d, T, parity, dt_fixed, s, ev0, ev1);
-    }
+    const bool w = d.w10n > 0, c = d.eta_lo != nullptr;
+    if (stage == 1) return proj ? launch_stage_pc<1, true>(w, c, d, T, parity, dt_fixed, s, ev0, ev1)
+                                : launch_stage_pc<1, false>(w, c, d, T, parity, dt_fixed, s, ev0, ev1);
+    return proj ? launch_stage_pc<2, true>(w, c, d, T, parity, dt_fixed, s, ev0, ev1)
+                : launch_stage_pc<2, false>(w, c, d, T, parity, dt_fixed, s, ev0, ev1);
 }
 
 // waves per SIMD that one stage kernel variant can keep resident, from its
 // register usage (512 VGPRs per SIMD lane on gfx950, 8-register granules)
-int stage_waves_per_simd(int stage, bool proj)
+int waves_of(const void *f)
 {
     hipFuncAttributes a{};
-    hipError_t e;
-    if (stage == 1) e = proj ? hipFuncGetAttributes(&a, (const void *)stage_kernel<1, true, false>)
-                             : hipFuncGetAttributes(&a, (const void *)stage_kernel<1, false, false>);
-    else e = proj ? hipFuncGetAttributes(&a, (const void *)stage_kernel<2, true, false>)
-                  : hipFuncGetAttributes(&a, (const void *)stage_kernel<2, false, false>);
-    if (e != hipSuccess || a.numRegs <= 0) return 3;
+    if (hipFuncGetAttributes(&a, f) != hipSuccess || a.numRegs <= 0) return 3;
     int regs = (a.numRegs + 7) / 8 * 8;
     int w = 512 / regs;
     return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
-template <int S, bool P, bool W>
+int stage_waves_per_simd(int stage, bool proj, bool comp)
+{
+    const void *f;
+    if (stage == 1) f = proj ? (comp ? (const void *)stage_kernel<1, true, false, true> : (const void *)stage_kernel<1, true, false, false>)
+                             : (comp ? (const void *)stage_kernel<1, false, false, true> : (const void *)stage_kernel<1, false, false, false>);
+    else f = proj ? (comp ? (const void *)stage_kernel<2, true, false, true> : (const void *)stage_kernel<2, true, false, false>)
+                  : (comp ? (const void *)stage_kernel<2, false, false, true> : (const void *)stage_kernel<2, false, false, false>);
+    return waves_of(f);
+}
+
+template <int S, bool P, bool W, bool C>
 hipError_t launch_ensemble_v(const EnsMember *mem, const EnsItem *items, EnsCtrl *ec, int parity, int chunk,
                              int nblocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     dim3 grid(nblocks), block(kWave * kWavesPerBlock);
-    if (ev0) hipExtLaunchKernelGGL(ensemble_kernel<S, P, W>, grid, block, 0, s, ev0, ev1, 0, mem, items, ec, parity, chunk);
-    else ensemble_kernel<S, P, W><<<grid, block, 0, s>>>(mem, items, ec, parity, chunk);
+    if (ev0)
+        hipExtLaunchKernelGGL(ensemble_kernel<S, P, W, C>, grid, block, 0, s, ev0, ev1, 0, mem, items, ec, parity, chunk);
+    else ensemble_kernel<S, P, W, C><<<grid, block, 0, s>>>(mem, items, ec, parity, chunk);
     return hipGetLastError();
 }
 
-hipError_t launch_ensemble(int stage, bool proj, bool w10, const EnsMember *mem, const EnsItem *items, EnsCtrl *ec,
-                           int parity, int chunk, int nblocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+template <int S, bool P>
+hipError_t launch_ensemble_pc(bool w, bool c, const EnsMember *mem, const EnsItem *items, EnsCtrl *ec, int parity,
+                              int chunk, int nblocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    switch ((stage == 2 ? 4 : 0) | (proj ? 2 : 0) | (w10 ? 1 : 0)) {
-    case 0: return launch_ensemble_v<1, false, false>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
-    case 1: return launch_ensemble_v<1, false, true>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
-    case 2: return launch_ensemble_v<1, true, false>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
-    case 3: return launch_ensemble_v<1, true, true>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
-    case 4: return launch_ensemble_v<2, false, false>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
-    case 5: return launch_ensemble_v<2, false, true>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
-    case 6: return launch_ensemble_v<2, true, false>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
-    default: return launch_ensemble_v<2, true, true>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
-    }
+    if (c) return w ? launch_ensemble_v<S, P, true, true>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1)
+                    : launch_ensemble_v<S, P, false, true>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
+    return w ? launch_ensemble_v<S, P, true, false>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1)
+             : launch_ensemble_v<S, P, false, false>(mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
 }
 
-int ensemble_waves_per_simd(int stage, bool proj)
+hipError_t launch_ensemble(int stage, bool proj, bool w10, bool comp, const EnsMember *mem, const EnsItem *items,
+                           EnsCtrl *ec, int parity, int chunk, int nblocks, hipStream_t s, hipEvent_t ev0,
+                           hipEvent_t ev1)
 {
-    hipFuncAttributes a{};
-    hipError_t e;
-    if (stage == 1) e = proj ? hipFuncGetAttributes(&a, (const void *)ensemble_kernel<1, true, false>)
-                             : hipFuncGetAttributes(&a, (const void *)ensemble_kernel<1, false, false>);
-    else e = proj ? hipFuncGetAttributes(&a, (const void *)ensemble_kernel<2, true, false>)
-                  : hipFuncGetAttributes(&a, (const void *)ensemble_kernel<2, false, false>);
-    if (e != hipSuccess || a.numRegs <= 0) return 3;
-    int regs = (a.numRegs + 7) / 8 * 8;
-    int w = 512 / regs;
-    return w < 1 ? 1 : (w > 8 ? 8 : w);
+    if (stage == 1)
+        return proj ? launch_ensemble_pc<1, true>(w10, comp, mem, items, ec, parity, chunk, nblocks, s, ev0, ev1)
+                    : launch_ensemble_pc<1, false>(w10, comp, mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
+    return proj ? launch_ensemble_pc<2, true>(w10, comp, mem, items, ec, parity, chunk, nblocks, s, ev0, ev1)
+                : launch_ensemble_pc<2, false>(w10, comp, mem, items, ec, parity, chunk, nblocks, s, ev0, ev1);
+}
+
+int ensemble_waves_per_simd(int stage, bool proj, bool comp)
+{
+    const void *f;
+    if (stage == 1) f = proj ? (comp ? (const void *)ensemble_kernel<1, true, false, true> : (const void *)ensemble_kernel<1, true, false, false>)
+                             : (comp ? (const void *)ensemble_kernel<1, false, false, true> : (const void *)ensemble_kernel<1, false, false, false>);
+    else f = proj ? (comp ? (const void *)ensemble_kernel<2, true, false, true> : (const void *)ensemble_kernel<2, true, false, false>)
+                  : (comp ? (const void *)ensemble_kernel<2, false, false, true> : (const void *)ensemble_kernel<2, false, false, false>);
+    return waves_of(f);
 }
 
 hipError_t launch_cfl(const Dom &d, int slot, hipStream_t s)

@@ -36,7 +36,7 @@ class Params(C.Structure):
         ("courant", C.c_double), ("theta", C.c_double), ("kappa", C.c_double),
         ("bc", C.c_int32 * 4), ("friction", C.c_int32), ("friction_coeff", C.c_double),
         ("rho_w", C.c_double), ("frs_width", C.c_int32), ("frs_d0", C.c_double),
-        ("north_projection", C.c_int32),
+        ("north_projection", C.c_int32), ("compensated_state", C.c_int32),
     ]
 
 
@@ -156,7 +156,8 @@ def _fp(a: Optional[np.ndarray]):
 
 def make_params(nx, ny, dx, dy, *, g=9.81, courant=0.45, theta=1.3, kappa=1e-3,
                 bc: Sequence[int] = (BC_WALL,) * 4, friction=FRICTION_NONE, friction_coeff=0.0,
-                rho_w=1025.0, frs_width=10, frs_d0=2.0, north_projection=False) -> Params:
+                rho_w=1025.0, frs_width=10, frs_d0=2.0, north_projection=False,
+                compensated_state=False) -> Params:
     p = Params()
     p.nx, p.ny, p.dx, p.dy, p.g = int(nx), int(ny), float(dx), float(dy), float(g)
     p.courant, p.theta, p.kappa = float(courant), float(theta), float(kappa)
@@ -165,6 +166,7 @@ def make_params(nx, ny, dx, dy, *, g=9.81, courant=0.45, theta=1.3, kappa=1e-3,
     p.friction, p.friction_coeff = int(friction), float(friction_coeff)
     p.rho_w, p.frs_width, p.frs_d0 = float(rho_w), int(frs_width), float(frs_d0)
     p.north_projection = 1 if north_projection else 0
+    p.compensated_state = 1 if compensated_state else 0
     return p
 
 
@@ -206,13 +208,14 @@ class Domain:
         self._h = h
 
     @classmethod
-    def from_workload(cls, wl, *, north_projection=False, max_wind_times=None, max_bnd_times=None,
+    def from_workload(cls, wl, *, north_projection=False, compensated_state=False, max_wind_times=None,
+                      max_bnd_times=None,
                       device=None, stream=None) -> "Domain":
         p = make_params(wl.nx, wl.ny, wl.dx, wl.dy, g=wl.g, courant=wl.courant, theta=wl.theta,
                         kappa=wl.kappa, bc=wl.bc, friction=wl.friction,
                         friction_coeff=wl.friction_coeff, rho_w=wl.rho_w,
                         frs_width=wl.frs_width, frs_d0=wl.frs_d0,
-                        north_projection=north_projection)
+                        north_projection=north_projection, compensated_state=compensated_state)
         nw = len(wl.wind_t)
         nb = 0 if wl.bnd is None else len(wl.bnd_t)
         dom = cls(p, wl.Hc, wl.f, wl.eta, wl.hu, wl.hv, land=wl.land, north=wl.north,

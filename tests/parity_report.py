@@ -5,6 +5,7 @@ test suite).
     python tests/parity_report.py oracle CONFIG DIR   # CPU: FP64 oracle, own dt
     python tests/parity_report.py gpu CONFIG DIR      # GPU: own dt, and dt replay
                                                       #      if DIR has the oracle's dts
+    python tests/parity_report.py gpucomp CONFIG DIR  # the same with the compensated state
     python tests/parity_report.py compare CONFIG DIR  # per-field relative L2 / Linf
     python tests/parity_report.py fp32state CONFIG DIR
         # the FP64 oracle with its state rounded to float32 after every step,
@@ -61,12 +62,13 @@ def run_oracle(name, out):
                       "cell_updates_per_s": wl.nx * wl.ny * k / el, "threads": orc.num_threads()}), flush=True)
 
 
-def run_gpu(name, out):
+def run_gpu(name, out, comp=False):
     import torch
     from paper_1912_02457_amd import Domain
     torch.cuda.set_device(0)
     wl = workload(name)
-    d = Domain.from_workload(wl, device="cuda:0")
+    tag = "comp_" if comp else ""
+    d = Domain.from_workload(wl, device="cuda:0", compensated_state=comp)
     t0 = time.time()
     if wl.t_end:
         k = d.run_until(wl.t_end)
@@ -76,16 +78,16 @@ def run_gpu(name, out):
     e, u, v, t, _ = d.read_state()
     el = time.time() - t0
     d.close()
-    np.savez_compressed(os.path.join(out, f"{name}_gpu_own.npz"), eta=e, hu=u, hv=v, t=t, steps=k)
+    np.savez_compressed(os.path.join(out, f"{name}_gpu_{tag}own.npz"), eta=e, hu=u, hv=v, t=t, steps=k)
     info = {"config": name, "gpu_steps": k, "t": t, "seconds": el}
     ref = os.path.join(out, f"{name}_oracle.npz")
     if os.path.exists(ref):
         dts = np.load(ref)["dts"]
-        d = Domain.from_workload(wl, device="cuda:0")
+        d = Domain.from_workload(wl, device="cuda:0", compensated_state=comp)
         d.step_dt(dts)
         e, u, v, t, _ = d.read_state()
         d.close()
-        np.savez_compressed(os.path.join(out, f"{name}_gpu_replay.npz"), eta=e, hu=u, hv=v, t=t)
+        np.savez_compressed(os.path.join(out, f"{name}_gpu_{tag}replay.npz"), eta=e, hu=u, hv=v, t=t)
         info["replay_steps"] = len(dts)
     print(json.dumps(info), flush=True)
 
@@ -96,7 +98,7 @@ def compare(name, out):
     ref = np.load(os.path.join(out, f"{name}_oracle.npz"))
     refst = (ref["eta"], ref["hu"], ref["hv"])
     res = {"config": name, "oracle_t": float(ref["t"]), "steps": int(len(ref["dts"]))}
-    for mode in ("own", "replay"):
+    for mode in ("own", "replay", "comp_own", "comp_replay"):
         p = os.path.join(out, f"{name}_gpu_{mode}.npz")
         if os.path.exists(p):
             g = np.load(p)
@@ -128,4 +130,5 @@ def run_fp32state(name, out):
 if __name__ == "__main__":
     mode, name, out = sys.argv[1], sys.argv[2], sys.argv[3]
     os.makedirs(out, exist_ok=True)
-    {"oracle": run_oracle, "gpu": run_gpu, "compare": compare, "fp32state": run_fp32state}[mode](name, out)
+    {"oracle": run_oracle, "gpu": run_gpu, "gpucomp": lambda n, o: run_gpu(n, o, comp=True), "compare": compare,
+     "fp32state": run_fp32state}[mode](name, out)

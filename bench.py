@@ -83,8 +83,14 @@ def parse():
                     help="only run warmup + this many steps (for rocprofv3 runs), no JSON")
     ap.add_argument("--no-preprocess", action="store_true")
     ap.add_argument("--no-strip", action="store_true", help="skip the one-strip-of-8 measurement")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the domain-size sweep")
+    ap.add_argument("--sweep-max", type=int, default=8192,
+                    help="largest N of the N x N size sweep (powers of two from 512; 16384 needs ~30 GB of host memory)")
+    ap.add_argument("--sweep-steps", type=int, default=100)
     ap.add_argument("--no-compensated", action="store_true",
                     help="skip the measurement of the compensated-state variant")
+    ap.add_argument("--count-tilings", action="store_true",
+                    help="profiler run: 3 steps at every tiling the tuner may choose (no tuning, no timing)")
     ap.add_argument("--compensated", action="store_true",
                     help="with --profile-steps: profile the compensated-state kernels instead")
     ap.add_argument("--preprocess-only", action="store_true",
@@ -145,11 +151,12 @@ def error_vs_oracle(wl, ref, t_ref, steps, np, compensated=False):
     return out
 
 
-def measured_traffic(kernel: str, rows: int):
-    """HBM bytes per launch of ``kernel`` at ``rows`` rows per tile from the
-    committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by the
-    copy-kernel calibration), or None when the kernel source changed since
-    they were taken."""
+def measured_traffic(kernel: str, rows: int, tail_rpw: int = 0, tail_rows: int = 0):
+    """HBM bytes per launch of ``kernel`` under a tiling (rows per tile, and
+    the tail's rows per tile and rows) from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (scaled by the copy-kernel calibration), or
+    None when that tiling was not counted or the kernel source changed
+    since."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -160,8 +167,26 @@ def measured_traffic(kernel: str, rows: int):
     src = hashlib.sha1(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     if vals.get("kernel_source_sha1") != src:
         return None
-    key = f"{kernel}_rows{rows}_hbm_bytes_per_launch"
-    return float(vals[key]) if key in vals else None
+    # "- stage2_rows7: one 122797917; tail1x74 120760341; ..."
+    want = f"tail{tail_rpw}x{tail_rows}" if tail_rpw else "one"
+    for item in vals.get(f"{kernel}_rows{rows}", "").split(";"):
+        parts = item.split()
+        if len(parts) == 2 and parts[0] == want:
+            return float(parts[1])
+    return None
+
+
+def _copy_calibration(a, torch):
+    """Three device-to-device copies of 256 MiB: the reference a profiler's
+    HBM byte counters are scaled by."""
+    if not a.copy_calibration:
+        return
+    x = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
 
 
 def bench_single(a, np, torch):
@@ -173,23 +198,31 @@ def bench_single(a, np, torch):
     land_cells = int(np.count_nonzero(wl.land)) if wl.land is not None else 0
     wet_cells = cells - land_cells
     dom = Domain.from_workload(wl, device="cuda:0", compensated_state=a.compensated and a.profile_steps > 0)
-    dom.autotune()  # measured tile height (does not advance the simulation)
-    rows_per_wave, tile_order, waves = dom.tiling(1)
-    rows2, _, waves2 = dom.tiling(2)
+    if a.count_tilings:
+        # every tiling the tuner may settle on, 3 steps each, in list order
+        # (stage k's dispatches 3i .. 3i+2 ran at its list entry i, or its last)
+        l1, l2 = dom.list_tilings(1), dom.list_tilings(2)
+        for i in range(max(len(l1), len(l2))):
+            dom.set_stage_tiling(1, *l1[min(i, len(l1) - 1)])
+            dom.set_stage_tiling(2, *l2[min(i, len(l2) - 1)])
+            dom.step(3)
+        torch.cuda.synchronize()
+        _copy_calibration(a, torch)
+        dom.close()
+        print(json.dumps({"counted_tilings": [l1, l2], "steps_per_tiling": 3}), flush=True)
+        return None, wl
+    dom.autotune()  # measured tiling (does not advance the simulation)
+    rows_per_wave, tail_rpw1, tail_rows1, tile_order, waves = dom.stage_tiling(1)
+    rows2, tail_rpw2, tail_rows2, _, waves2 = dom.stage_tiling(2)
 
     dom.step(a.warmup)
     torch.cuda.synchronize()
     if a.profile_steps:
         dom.step(a.profile_steps)
         torch.cuda.synchronize()
-        if a.copy_calibration:
-            x = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0").fill_(1.0)
-            y = torch.empty_like(x)
-            torch.cuda.synchronize()
-            for _ in range(3):
-                y.copy_(x)
-            torch.cuda.synchronize()
-        print(f"profiled {a.profile_steps} steps", flush=True)
+        _copy_calibration(a, torch)
+        print(json.dumps({"profiled_steps": a.profile_steps,
+                          "stage_tiling": [dom.stage_tiling(1), dom.stage_tiling(2)]}), flush=True)
         return None, wl
 
     # timed region: K steps through the captured HIP graphs of the stage
@@ -225,7 +258,8 @@ def bench_single(a, np, torch):
     gbs = bytes_dom / (ms_dom * 1e-3) / 1e9
     slots_dom = VALU_SLOTS_PER_CELL[dominant] * cells
     achieved = slots_dom / (ms_dom * 1e-3) / 1e12
-    traffic = measured_traffic(f"stage{dominant}", rows_per_wave if dominant == 1 else rows2)
+    traffic = measured_traffic(f"stage{dominant}", *((rows_per_wave, tail_rpw1, tail_rows1) if dominant == 1
+                                                     else (rows2, tail_rpw2, tail_rows2)))
 
     value = cells * a.steps / el
     out = {
@@ -246,7 +280,8 @@ def bench_single(a, np, torch):
             "nx": wl.nx, "ny": wl.ny, "dx_m": wl.dx, "cells": cells, "land_fraction": land_cells / cells,
             "boundaries": "nested (M2 tide, hourly snapshots) on all sides", "friction": "linear r=3e-3 m/s",
             "wind_stress_Nm2": 0.1, "courant": wl.courant, "dt_s": dt_next,
-            "rows_per_wave": [rows_per_wave, rows2], "tile_order": tile_order, "waves_per_stage": [waves, waves2],
+            "rows_per_wave": [rows_per_wave, rows2], "tail_rows_per_wave": [tail_rpw1, tail_rpw2],
+            "tail_rows": [tail_rows1, tail_rows2], "tile_order": tile_order, "waves_per_stage": [waves, waves2],
             "tiling": "measured per stage kernel before the timed region (swe_autotune_tiling)",
         },
         "roofline": {
@@ -323,12 +358,69 @@ def bench_compensated(a, np, torch, wl, full_value):
     dom.stage_times(reset=True)
     dom.step(min(a.steps, 1000))
     ms1, ms2, _ = dom.stage_times(reset=True)
-    rows = [dom.tiling(1)[0], dom.tiling(2)[0]]
+    rows = [dom.stage_tiling(1)[:3], dom.stage_tiling(2)[:3]]
     dom.close()
     v = wl.nx * wl.ny * a.steps / el
     return {"value": v, "unit": "cell-updates/s", "ms_per_step": el / a.steps * 1e3, "steps": a.steps,
             "stage1_ms": ms1, "stage2_ms": ms2, "rows_per_wave": rows, "rate_vs_float32_state": v / full_value,
             "note": "same workload and timed region as the headline, compensated_state=1"}
+
+
+# Total simulation times of the grid-convergence benchmark on a Tesla P100,
+# from the appendix table of timings (N x N cells, 1600 simulated seconds at
+# dt = 1600/N s, i.e. N steps): context for the size sweep, other hardware.
+PAPER_P100_TOTAL_S = {512: 0.169710, 1024: 1.170814, 2048: 9.133564, 4096: 72.832028,
+                      8192: 582.599290, 16384: 4695.904546}
+
+
+def bench_sweep(a, np, torch):
+    """The paper's own benchmark shape: the grid-convergence case (peaks
+    bathymetry, cosine bump, latitude and north angle from a pole, walls) at
+    N x N for N = 512 .. sweep_max, each run for sweep_steps steps after
+    warm-up through the captured graphs.  Per size: cell-updates/s, the stage
+    kernels' event-timed durations, algorithmic HBM rate, and the time the
+    paper's run (N steps) would take at this rate next to the P100's."""
+    from paper_1912_02457_amd import Domain
+    from workloads import convergence_case
+    out = []
+    N = 512
+    while N <= a.sweep_max:
+        t_gen = time.perf_counter()
+        wl = convergence_case(N)
+        t_gen = time.perf_counter() - t_gen
+        dom = Domain.from_workload(wl, device="cuda:0")
+        del wl
+        dom.autotune()
+        dom.step(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dom.step(a.sweep_steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        dom.enable_timing(True)
+        dom.stage_times(reset=True)
+        dom.step(a.sweep_steps)
+        ms1, ms2, _ = dom.stage_times(reset=True)
+        rows = [dom.stage_tiling(1)[:3], dom.stage_tiling(2)[:3]]
+        e, _, _, _, _ = dom.read_state()
+        finite = bool(np.isfinite(e).all())
+        dom.close()
+        cells = N * N
+        v = cells * a.sweep_steps / el
+        gbs2 = BYTES[2][0] * cells / (ms2 * 1e-3) / 1e9
+        gbs1 = BYTES[1][0] * cells / (ms1 * 1e-3) / 1e9
+        paper_run = N * el / a.sweep_steps
+        out.append({"n": N, "cells": cells, "value": v, "ms_per_step": el / a.sweep_steps * 1e3,
+                    "stage1_ms": ms1, "stage2_ms": ms2, "rows_per_wave": rows,
+                    "hbm_frac_stage1": gbs1 / HBM_PEAK_GBS, "hbm_frac_stage2": gbs2 / HBM_PEAK_GBS,
+                    "paper_run_s": paper_run, "paper_p100_total_s": PAPER_P100_TOTAL_S.get(N),
+                    "state_finite": finite, "input_generation_s": t_gen})
+        _progress(f"sweep {N}^2: {v:.3e} cell-updates/s")
+        N *= 2
+    return {"workload": "grid-convergence case (peaks bathymetry, cosine bump, pole latitude/north, walls), N x N",
+            "steps": a.sweep_steps, "sizes": out,
+            "note": "paper_run_s = N steps (1600 s at dt = 1600/N) at the measured rate; "
+                    "paper_p100_total_s is the paper's Tesla P100 total (context, other hardware)"}
 
 
 def _member(k):
@@ -697,6 +789,8 @@ def main():
     if not a.no_strip:
         out["strip_of_8"] = bench_strip(a, np, torch, wl, out["value"])
         _progress(f"strip: {out['strip_of_8']['value']:.3e} cell-updates/s")
+    if not a.no_sweep:
+        out["size_sweep"] = bench_sweep(a, np, torch)
     if not a.no_compensated:
         out["compensated_state"] = bench_compensated(a, np, torch, wl, out["value"])
         _progress(f"compensated: {out['compensated_state']['value']:.3e} cell-updates/s")

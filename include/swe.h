@@ -220,7 +220,8 @@ int swe_diagnostics(swe_domain *d, double *mass, double *energy);
 int swe_status(swe_domain *d);
 
 /* Measures both stage kernels of this domain for rows per tile in {2..64}
- * (a few launches each) and keeps the fastest per stage.  The state and the
+ * and, around the fastest, for tails of 1-4-row bands (swe_set_stage_tiling;
+ * a few launches each) and keeps the fastest tiling per stage.  The state and the
  * control block are saved to host memory first and restored afterwards, so
  * the simulation does not advance.  *rows_per_wave gets stage 1's choice
  * (may be NULL; swe_get_tiling reports each stage).  Synchronises.  Errors:
@@ -238,6 +239,31 @@ int swe_autotune_tiling(swe_domain *d, int32_t *rows_per_wave);
  * wavefronts per launch of stage kernel `stage` (1 or 2). */
 int swe_set_tiling(swe_domain *d, int32_t rows_per_wave, int32_t order);
 int swe_get_tiling(swe_domain *d, int32_t stage, int32_t *rows_per_wave, int32_t *order, int32_t *waves);
+
+/* Tiling of one stage kernel (1 or 2) with two band heights: bands of
+ * rows_per_wave rows (>= 1) from the top, and when 0 < tail_rows_per_wave <
+ * rows_per_wave, the last rows -- at least tail_rows of them, 0 < tail_rows <
+ * ny, with at least one band of rows_per_wave rows before them -- in bands of
+ * tail_rows_per_wave rows whose waves are launched after all the others, so
+ * that a launch ends on short waves.  Other tail values give one band height.
+ * order as in swe_set_tiling (-1 keeps the current one).  Results do not
+ * depend on it (bitwise).  swe_get_stage_tiling reports the values (tail
+ * rows per wave and the number of tail rows 0 for one band height) and the
+ * wavefronts per launch; any output pointer may be NULL.  Errors: SWE_E_ARG,
+ * SWE_E_STATE inside an ensemble. */
+int swe_set_stage_tiling(swe_domain *d, int32_t stage, int32_t rows_per_wave, int32_t tail_rows_per_wave,
+                         int32_t tail_rows, int32_t order);
+
+/* Every tiling swe_autotune_tiling may time for stage kernel `stage` on this
+ * domain (the one-height tilings, then the tails tried around each height),
+ * as triples (rows_per_wave, tail_rows_per_wave, tail_rows) in the form of
+ * swe_get_stage_tiling, into out[3 * max_tilings] (caller-owned host array;
+ * NULL when max_tilings is 0).  *n_tilings gets the total count, which may
+ * exceed max_tilings (then only the first max_tilings are written).  Lets a
+ * profiler run cover every tiling the tuner can settle on.  Errors: SWE_E_ARG. */
+int swe_list_tilings(swe_domain *d, int32_t stage, int32_t *out, int32_t max_tilings, int32_t *n_tilings);
+int swe_get_stage_tiling(swe_domain *d, int32_t stage, int32_t *rows_per_wave, int32_t *tail_rows_per_wave,
+                         int32_t *tail_rows, int32_t *order, int32_t *waves);
 
 /* Average device time per launch of each stage kernel (milliseconds) over
  * the launches issued since the last call with reset != 0, measured with HIP

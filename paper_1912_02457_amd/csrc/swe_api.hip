@@ -786,40 +786,157 @@ int swe_set_tiling(swe_domain *d, int32_t rows_per_wave, int32_t order)
     return SWE_OK;
 }
 
-// Time one stage kernel over candidate tile heights (one warm-up and eight
-// event-timed launches each, compared by their median so that a disturbed
-// launch does not decide); returns the fastest.
-int sweep_stage(swe_domain *d, int stage, int *best_by)
+int swe_set_stage_tiling(swe_domain *d, int32_t stage, int32_t rows_per_wave, int32_t tail_rows_per_wave,
+                         int32_t tail_rows, int32_t order)
 {
-    static const int cand[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 32, 48, 64};
-    constexpr int kReps = 8;
-    const bool proj = d->p.north_projection != 0;
-    hipEvent_t ev[2 * kReps];
-    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
-    int best = d->T[stage - 1].by;
-    float best_ms = INFINITY;
-    hipError_t he = hipSuccess;
-    for (int by : cand) {
-        if (by > d->p.ny && by != cand[0]) break;
-        Tiling T = make_tiling(d->p.nx, d->p.ny, by);
-        if ((he = launch_stage(stage, proj, d->dom, T, d->parity, 0.0, d->stream, nullptr, nullptr)) != hipSuccess)
-            break;
+    if (!d) return fail(SWE_E_ARG, "domain is NULL");
+    if (d->ensemble) return fail(SWE_E_STATE, "domain belongs to an ensemble");
+    if (stage != 1 && stage != 2) return fail(SWE_E_ARG, "stage must be 1 or 2");
+    if (rows_per_wave < 1 || rows_per_wave > 4096) return fail(SWE_E_ARG, "rows_per_wave must be in [1, 4096]");
+    if (tail_rows_per_wave < 0 || tail_rows_per_wave > 4096 || tail_rows < 0)
+        return fail(SWE_E_ARG, "tail_rows_per_wave must be in [0, 4096] and tail_rows >= 0");
+    if (order < -1 || order > 3) return fail(SWE_E_ARG, "order must be -1 (default) or 0..3");
+    Tiling &T = d->T[stage - 1];
+    const int o = order >= 0 ? order : T.order;
+    T = make_tiling_tail(d->p.nx, d->p.ny, rows_per_wave, tail_rows_per_wave, tail_rows);
+    T.order = o;
+    drop_graphs(d);
+    return SWE_OK;
+}
+
+int swe_get_stage_tiling(swe_domain *d, int32_t stage, int32_t *rows_per_wave, int32_t *tail_rows_per_wave,
+                         int32_t *tail_rows, int32_t *order, int32_t *waves)
+{
+    if (!d) return fail(SWE_E_ARG, "domain is NULL");
+    if (stage != 1 && stage != 2) return fail(SWE_E_ARG, "stage must be 1 or 2");
+    const Tiling &T = d->T[stage - 1];
+    const bool two = T.nrb1 < T.nrb;
+    if (rows_per_wave) *rows_per_wave = T.by;
+    if (tail_rows_per_wave) *tail_rows_per_wave = two ? T.by2 : 0;
+    if (tail_rows) *tail_rows = two ? d->p.ny - T.nrb1 * T.by : 0;
+    if (order) *order = T.order;
+    if (waves) *waves = T.ntiles;
+    return SWE_OK;
+}
+
+// Median-based time of one stage kernel under tiling T (one warm-up and
+// eight event-timed launches, the middle two summed, so that a disturbed
+// launch does not decide).
+struct StageTimer {
+    static constexpr int kReps = 8;
+    hipEvent_t ev[2 * kReps] = {};
+    int made = 0;
+    ~StageTimer() { for (int k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]); }
+    hipError_t init()
+    {
+        for (; made < 2 * kReps; ++made) {
+            hipError_t e = hipEventCreate(&ev[made]);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    hipError_t time(swe_domain *d, int stage, const Tiling &T, float *out)
+    {
+        const bool proj = d->p.north_projection != 0;
+        hipError_t he = launch_stage(stage, proj, d->dom, T, d->parity, 0.0, d->stream, nullptr, nullptr);
         for (int k = 0; k < kReps && he == hipSuccess; ++k)
             he = launch_stage(stage, proj, d->dom, T, d->parity, 0.0, d->stream, ev[2 * k], ev[2 * k + 1]);
-        if (he != hipSuccess || (he = hipStreamSynchronize(d->stream)) != hipSuccess) break;
+        if (he != hipSuccess || (he = hipStreamSynchronize(d->stream)) != hipSuccess) return he;
         float ms[kReps];
         for (int k = 0; k < kReps && he == hipSuccess; ++k) {
             ms[k] = 0.f;
             he = hipEventElapsedTime(&ms[k], ev[2 * k], ev[2 * k + 1]);
         }
-        if (he != hipSuccess) break;
+        if (he != hipSuccess) return he;
         std::sort(ms, ms + kReps);
-        const float tot = ms[kReps / 2 - 1] + ms[kReps / 2];
-        if (tot < best_ms * 0.99f) { best_ms = tot; best = by; }
+        *out = ms[kReps / 2 - 1] + ms[kReps / 2];
+        return hipSuccess;
     }
-    for (auto &e : ev) (void)hipEventDestroy(e);
+};
+
+// Time one stage kernel over candidate tilings and return the fastest: first
+// one band height for the whole domain (2 .. 64 rows), then, around the best
+// height and the next two taller ones, a tail of short bands (1 to 4 rows)
+// at the end of the launch holding about a quarter, a half, one or two
+// rounds of the wave slots the kernel's register use allows.  A candidate replaces the
+// incumbent only when it is more than 1 % faster.
+constexpr int kTileHeights[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 32, 48, 64};
+constexpr int kNumTileHeights = sizeof(kTileHeights) / sizeof(kTileHeights[0]);
+
+// The tail tilings the sweep tries with head bands of `by` rows: tails of
+// 1..4-row bands holding about a quarter, a half, one or two rounds of the
+// stage kernel's resident wave slots; duplicates dropped.
+void tail_candidates(const swe_domain *d, int stage, int by, std::vector<Tiling> &out)
+{
+    const int nx = d->p.nx, ny = d->p.ny;
+    const double slots = (double)d->cus * 4 * d->wps[stage - 1];
+    const int nstrips = (nx + kStrip - 1) / kStrip;
+    const size_t first = out.size();
+    for (int by2 = 1; by2 <= 4 && by2 < by; ++by2) {
+        for (double rounds : {0.25, 0.5, 1.0, 2.0}) {
+            const int bands = (int)std::lround(rounds * slots / nstrips);
+            const int tail = std::max(1, bands) * by2;
+            if (tail + by > ny) continue;
+            const Tiling T = make_tiling_tail(nx, ny, by, by2, tail);
+            if (T.nrb1 == T.nrb) continue;
+            bool dup = false;
+            for (size_t k = first; k < out.size(); ++k) dup |= out[k].by2 == T.by2 && out[k].nrb1 == T.nrb1;
+            if (!dup) out.push_back(T);
+        }
+    }
+}
+
+// Time one stage kernel over candidate tilings and return the fastest: first
+// one band height for the whole domain (2 .. 64 rows), then the tails of
+// tail_candidates around the best height and the next two taller ones.  A
+// candidate replaces the incumbent only when it is more than 1 % faster.
+int sweep_stage(swe_domain *d, int stage, Tiling *best_T)
+{
+    const int nx = d->p.nx, ny = d->p.ny;
+    StageTimer tm;
+    hipError_t he = tm.init();
+    Tiling best = d->T[stage - 1];
+    float best_ms = INFINITY;
+    int best_k = -1;
+    for (int k = 0; k < kNumTileHeights && he == hipSuccess; ++k) {
+        if (kTileHeights[k] > ny && k != 0) break;
+        const Tiling T = make_tiling(nx, ny, kTileHeights[k]);
+        float ms = 0.f;
+        if ((he = tm.time(d, stage, T, &ms)) != hipSuccess) break;
+        if (ms < best_ms * 0.99f) { best_ms = ms; best = T; best_k = k; }
+    }
+    std::vector<Tiling> tails;
+    for (int k = best_k; k >= 0 && k < best_k + 3 && k < kNumTileHeights; ++k)
+        tail_candidates(d, stage, kTileHeights[k], tails);
+    for (size_t k = 0; k < tails.size() && he == hipSuccess; ++k) {
+        float ms = 0.f;
+        if ((he = tm.time(d, stage, tails[k], &ms)) != hipSuccess) break;
+        if (ms < best_ms * 0.99f) { best_ms = ms; best = tails[k]; }
+    }
     if (he != hipSuccess) return hip_fail(he, "tiling sweep");
-    *best_by = best;
+    *best_T = best;
+    return SWE_OK;
+}
+
+int swe_list_tilings(swe_domain *d, int32_t stage, int32_t *out, int32_t max_tilings, int32_t *n_tilings)
+{
+    if (!d) return fail(SWE_E_ARG, "domain is NULL");
+    if (stage != 1 && stage != 2) return fail(SWE_E_ARG, "stage must be 1 or 2");
+    if (max_tilings < 0 || (max_tilings > 0 && !out)) return fail(SWE_E_ARG, "bad output array");
+    std::vector<Tiling> all;
+    for (int k = 0; k < kNumTileHeights; ++k) {
+        if (kTileHeights[k] > d->p.ny && k != 0) break;
+        all.push_back(make_tiling(d->p.nx, d->p.ny, kTileHeights[k]));
+    }
+    const size_t uniform = all.size();
+    for (size_t k = 0; k < uniform; ++k) tail_candidates(d, stage, all[k].by, all);
+    for (size_t k = 0; k < all.size() && (int)k < max_tilings; ++k) {
+        const bool two = all[k].nrb1 < all[k].nrb;
+        out[3 * k] = all[k].by;
+        out[3 * k + 1] = two ? all[k].by2 : 0;
+        out[3 * k + 2] = two ? d->p.ny - all[k].nrb1 * all[k].by : 0;
+    }
+    if (n_tilings) *n_tilings = (int32_t)all.size();
     return SWE_OK;
 }
 
@@ -840,12 +957,12 @@ int swe_autotune_tiling(swe_domain *d, int32_t *rows_per_wave)
     const int nq = d->p.compensated_state ? 6 : 3;
     for (int k = 0; k < nq; ++k)
         HIP_TRY(hipMemcpy2DAsync(d->pinned_state + k * plane, row, q[k], dp, row, ny, hipMemcpyDeviceToHost, d->stream));
-    int by1 = 0, by2 = 0;
-    rc = sweep_stage(d, 1, &by1);
+    Tiling T1 = d->T[0], T2 = d->T[1];
+    rc = sweep_stage(d, 1, &T1);
     if (!rc) {
-        hipError_t e = launch_stage(1, d->p.north_projection != 0, d->dom, make_tiling(nx, ny, by1), d->parity, 0.0,
-                                    d->stream, nullptr, nullptr);
-        rc = e != hipSuccess ? hip_fail(e, "launch_stage") : sweep_stage(d, 2, &by2);
+        hipError_t e = launch_stage(1, d->p.north_projection != 0, d->dom, T1, d->parity, 0.0, d->stream, nullptr,
+                                    nullptr);
+        rc = e != hipSuccess ? hip_fail(e, "launch_stage") : sweep_stage(d, 2, &T2);
     }
     // the state and control block go back even when the sweep failed
     for (int k = 0; k < nq; ++k)
@@ -853,10 +970,10 @@ int swe_autotune_tiling(swe_domain *d, int32_t *rows_per_wave)
     HIP_TRY(hipMemcpyAsync(d->dom.ctrl, &saved, sizeof(Ctrl), hipMemcpyHostToDevice, d->stream));
     HIP_TRY(hipStreamSynchronize(d->stream));
     if (rc) return rc;
-    d->T[0] = make_tiling(nx, ny, by1);
-    d->T[1] = make_tiling(nx, ny, by2);
+    d->T[0] = T1;
+    d->T[1] = T2;
     drop_graphs(d);
-    if (rows_per_wave) *rows_per_wave = by1;
+    if (rows_per_wave) *rows_per_wave = T1.by;
     return SWE_OK;
 }
 

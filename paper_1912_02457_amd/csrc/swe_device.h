@@ -104,12 +104,16 @@ struct Dom {
 };
 
 struct Tiling {
-    int by;       // rows per wave
+    int by;       // rows per wave of the head bands
     int order;    // bit 0: row-block-major tile numbering; bit 1: no XCD grouping
     int nstrips;  // ceil(nx / kStrip)
-    int nrb;      // ceil(ny / by)
+    int nrb;      // row bands in all
     int ntiles;   // nstrips * nrb
-    int nblocks;  // ceil(ntiles / kWavesPerBlock)
+    int nblocks;  // blocks of the launch
+    int by2;      // rows per wave of the tail bands (== by: one band height)
+    int nrb1;     // head bands, by rows each; bands nrb1 .. nrb-1 have by2 rows
+    int ntiles1;  // nstrips * nrb1: tiles 0 .. ntiles1-1 lie in the head
+    int nblk1;    // blocks 0 .. nblk1-1 hold the head tiles, the rest the tail
 };
 
 // Rows per wave for a domain.  A wave's work is proportional to its rows plus
@@ -131,6 +135,7 @@ inline int pick_rows_per_wave(int nx, int ny, int cus, int waves_per_simd)
     return best;
 }
 
+// One band height for the whole domain.
 inline Tiling make_tiling(int nx, int ny, int by)
 {
     Tiling t;
@@ -140,7 +145,76 @@ inline Tiling make_tiling(int nx, int ny, int by)
     t.nrb = (ny + by - 1) / by;
     t.ntiles = t.nstrips * t.nrb;
     t.nblocks = (t.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    t.by2 = by;
+    t.nrb1 = t.nrb;
+    t.ntiles1 = t.ntiles;
+    t.nblk1 = t.nblocks;
     return t;
+}
+
+// Two band heights: the first rows in bands of `by` rows (the head), the last
+// rows -- at least tail_rows of them -- in bands of by2 < by rows (the tail).
+// The head's tiles are launched first, so the waves that finish the launch
+// are the short tail waves: the drain at the end of a launch shrinks while
+// most rows keep the lower halo overhead of tall bands.  Falls back to one
+// band height when the arguments leave no head or no tail.
+inline Tiling make_tiling_tail(int nx, int ny, int by, int by2, int tail_rows)
+{
+    Tiling t = make_tiling(nx, ny, by);
+    if (by2 <= 0 || by2 >= by || tail_rows <= 0 || tail_rows >= ny) return t;
+    const int nrb1 = (ny - tail_rows) / by;
+    if (nrb1 <= 0) return t;
+    const int ytail = nrb1 * by;
+    t.by2 = by2;
+    t.nrb1 = nrb1;
+    t.nrb = nrb1 + (ny - ytail + by2 - 1) / by2;
+    t.ntiles1 = t.nstrips * nrb1;
+    t.ntiles = t.nstrips * t.nrb;
+    t.nblk1 = (t.ntiles1 + kWavesPerBlock - 1) / kWavesPerBlock;
+    t.nblocks = t.nblk1 + (t.ntiles - t.ntiles1 + kWavesPerBlock - 1) / kWavesPerBlock;
+    return t;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs.  Unless order bit 1 is
+// set, block b of a range of n blocks is renumbered so that each XCD gets a
+// contiguous run of the range (neighbouring tiles share halo rows in that
+// XCD's L2).  A bijection of [0, n).
+__host__ __device__ inline int xcd_group(int b, int n, int order)
+{
+    if (order & 2) return b;
+    const int q8 = n >> 3, r8 = n & 7, x8 = b & 7;
+    return x8 * q8 + (x8 < r8 ? x8 : r8) + (b >> 3);
+}
+
+// Tile of wave `wid` of block b, or -1 for a wave without one.  Head blocks
+// come first and carry only head tiles; each part is grouped per XCD on its own.
+__host__ __device__ inline int block_tile(const Tiling &T, int b, int wid)
+{
+    if (b < T.nblk1) {
+        const int t = xcd_group(b, T.nblk1, T.order) * kWavesPerBlock + wid;
+        return t < T.ntiles1 ? t : -1;
+    }
+    const int t = T.ntiles1 + xcd_group(b - T.nblk1, T.nblocks - T.nblk1, T.order) * kWavesPerBlock + wid;
+    return t < T.ntiles ? t : -1;
+}
+
+// Strip and rows [y0, y1) of a tile (0 <= tile < T.ntiles).  Within the head
+// and within the tail, tiles are numbered strip-major (order bit 0 clear) or
+// row-band-major.
+__host__ __device__ inline void tile_place(const Tiling &T, int tile, int ny, int &strip, int &y0, int &y1)
+{
+    int t = tile, nb = T.nrb1, by = T.by, base = 0;
+    if (tile >= T.ntiles1) {
+        t = tile - T.ntiles1;
+        nb = T.nrb - T.nrb1;
+        by = T.by2;
+        base = T.nrb1 * T.by;
+    }
+    int rb;
+    if (T.order & 1) { rb = t / T.nstrips; strip = t - rb * T.nstrips; }
+    else { strip = t / nb; rb = t - strip * nb; }
+    y0 = base + rb * by;
+    y1 = y0 + by < ny ? y0 + by : ny;
 }
 
 // ---- ensemble: many domains in one launch per stage ------------------------

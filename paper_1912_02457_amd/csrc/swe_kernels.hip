@@ -850,11 +850,9 @@ __device__ __forceinline__ void process_tile(const Dom &d, const Tiling &T, int 
     }
 
     const int nx = d.nx, ny = d.ny;
-    int strip, rb;
-    if (T.order & 1) { rb = tile / T.nstrips; strip = tile - rb * T.nstrips; }
-    else { strip = tile / T.nrb; rb = tile - strip * T.nrb; }
+    int strip, y0, y1;
+    tile_place(T, tile, ny, strip, y0, y1);
     const int x0 = strip * kStrip;
-    const int y0 = rb * T.by, y1 = min(y0 + T.by, ny);
     c.i = x0 - kHalo + lane;
     c.o = y0;
     c.out_lane = lane >= kHalo && lane < kWave - kHalo && c.i < nx;
@@ -899,18 +897,14 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Ti
     // the same in every lane of the wave: read as a scalar, so that the tile's
     // rows and columns, and with them the row offsets, are scalar values
     const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    // Blocks are dispatched round-robin over the 8 XCDs.  Order bit 1 clear:
-    // give each XCD a contiguous range of tiles so neighbouring tiles (which
-    // share halo rows) meet in the same L2.  Order bit 0: tiles numbered
-    // row-block-major (strips fastest) instead of strip-major.
-    const int nb = gridDim.x, b = blockIdx.x;
-    const int q8 = nb >> 3, r8 = nb & 7, x8 = b & 7;
-    const int L = (T.order & 2) ? b : x8 * q8 + min(x8, r8) + (b >> 3);
-    const int tile = L * kWavesPerBlock + wid;
+    // tile of this wave: head blocks before tail blocks, each part grouped
+    // per XCD (neighbouring tiles, which share halo rows, meet in one L2)
+    const int b = blockIdx.x;
+    const int tile = block_tile(T, b, wid);
 
     const StepTime st = step_time(d, parity, dt_fixed, lane);
     if (STAGE == 1 && b == 0 && wid == 0) advance_ctrl(d.ctrl, st, parity, lane);
-    if (st.skip || tile >= T.ntiles) return;
+    if (st.skip || tile < 0) return;
     process_tile<STAGE, PROJ, W10, COMP>(d, T, tile, parity, st, lane);
 }
 

@@ -88,6 +88,9 @@ SIGNATURES = {
     "swe_set_tiling": (C.c_int, [_VP, C.c_int32, C.c_int32]),
     "swe_get_tiling": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                  C.POINTER(C.c_int32)]),
+    "swe_set_stage_tiling": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "swe_get_stage_tiling": (C.c_int, [_VP, C.c_int32] + [C.POINTER(C.c_int32)] * 5),
+    "swe_list_tilings": (C.c_int, [_VP, C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]),
     "swe_autotune_tiling": (C.c_int, [_VP, C.POINTER(C.c_int32)]),
     "swe_enable_timing": (C.c_int, [_VP, C.c_int32]),
     "swe_stage_times": (C.c_int, [_VP, _D, _D, C.POINTER(C.c_int64), C.c_int32]),
@@ -337,9 +340,35 @@ class Domain:
     def set_tiling(self, rows_per_wave: int = 0, order: int = -1):
         _check(load_library().swe_set_tiling(self._h, int(rows_per_wave), int(order)))
 
+    def set_stage_tiling(self, stage: int, rows_per_wave: int, tail_rows_per_wave: int = 0, tail_rows: int = 0,
+                         order: int = -1):
+        """Tiling of one stage kernel: bands of rows_per_wave rows, and with
+        tail_rows_per_wave > 0 the last rows (at least tail_rows) in bands of
+        tail_rows_per_wave rows launched after the others."""
+        _check(load_library().swe_set_stage_tiling(self._h, int(stage), int(rows_per_wave), int(tail_rows_per_wave),
+                                                   int(tail_rows), int(order)))
+
+    def stage_tiling(self, stage: int):
+        """(rows per wave, tail rows per wave, tail rows, order, wavefronts per
+        launch) of a stage kernel; the tail values are 0 for one band height."""
+        v = [C.c_int32() for _ in range(5)]
+        _check(load_library().swe_get_stage_tiling(self._h, int(stage), *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def list_tilings(self, stage: int):
+        """Every (rows per wave, tail rows per wave, tail rows) the tuner may
+        time for a stage kernel on this domain."""
+        n = C.c_int32()
+        lib = load_library()
+        _check(lib.swe_list_tilings(self._h, int(stage), None, 0, C.byref(n)))
+        buf = (C.c_int32 * (3 * n.value))()
+        _check(lib.swe_list_tilings(self._h, int(stage), buf, n.value, C.byref(n)))
+        return [tuple(buf[3 * k:3 * k + 3]) for k in range(n.value)]
+
     def autotune(self) -> int:
-        """Time stage 1 over candidate tile heights (the simulation does not
-        advance) and keep the fastest; returns the rows per tile chosen."""
+        """Time both stage kernels over candidate tilings (the simulation does
+        not advance) and keep the fastest per stage; returns stage 1's rows per
+        tile."""
         r = C.c_int32()
         _check(load_library().swe_autotune_tiling(self._h, C.byref(r)))
         return r.value

@@ -393,6 +393,10 @@ def test_autotune_leaves_the_simulation_alone(which):
     before = a.read_state()
     by = a.autotune()
     assert by >= 2 and a.tiling()[0] == by
+    for st in (1, 2):  # the listing covers whatever the tuner settled on
+        lst = a.list_tilings(st)
+        assert a.stage_tiling(st)[:3] in lst and len(set(lst)) == len(lst)
+        assert all(t[1] == 0 for t in lst[:5])  # one-height tilings first (tails only where they fit)
     after = a.read_state()
     for x, y in zip(before, after):
         assert np.array_equal(x, y)
@@ -421,6 +425,42 @@ def test_tiling_does_not_change_results():
     for (_, st) in outs[1:]:
         for k in range(3):
             assert np.array_equal(st[k], outs[0][1][k])
+
+
+def test_two_band_heights_do_not_change_results():
+    """A tiling whose last rows are split into shorter bands launched after
+    the others (per stage kernel) gives bitwise the results of one band
+    height, for tails that are ragged, a single band, or most of the domain,
+    in every tile order; bad arguments are refused."""
+    from paper_1912_02457_amd import SweError
+    wl = random_small(190, 97, seed=21, land_frac=0.15, bc=(BC_NESTED, BC_WALL, BC_PERIODIC, BC_PERIODIC),
+                      friction=FRIC_MANNING, friction_coeff=0.03, wind=(0.1, -0.1))
+    d = _dom(wl)
+    d.set_tiling(8, 0)
+    d.step(20)
+    ref = d.read_state()
+    d.close()
+    for s1, s2, order in (((8, 2, 20), (5, 3, 9), 0), ((16, 4, 40), (12, 2, 1), 1), ((3, 2, 90), (64, 4, 33), 2),
+                          ((10, 3, 30), (7, 2, 50), 3)):
+        d = _dom(wl)
+        d.set_stage_tiling(1, *s1, order=order)
+        d.set_stage_tiling(2, *s2, order=order)
+        t1, t2 = d.stage_tiling(1), d.stage_tiling(2)
+        assert t1[0] == s1[0] and t1[1] == s1[1] and t1[2] >= s1[2] and t1[3] == order
+        assert t2[0] == s2[0] and t2[1] == s2[1] and t2[2] >= s2[2]
+        d.step(20)
+        got = d.read_state()
+        d.close()
+        _say("two band heights", s1, s2, order, t1, t2)
+        for k in range(4):
+            assert np.array_equal(got[k], ref[k]), (s1, s2, order, k)
+    d = _dom(wl)
+    d.set_stage_tiling(2, 8, 8, 30)  # tail not shorter: one band height
+    assert d.stage_tiling(2)[:3] == (8, 0, 0)
+    for bad in ((3, 8, 0, 0), (1, 0, 0, 0), (1, 8, -1, 0), (1, 8, 2, -5)):
+        with pytest.raises(SweError):
+            d.set_stage_tiling(*bad)
+    d.close()
 
 
 def test_max_size_domain_tiling_invariant_and_conserving():

@@ -213,7 +213,7 @@ def bench_single(a, np, torch):
         return None, wl
     dom.autotune()  # measured tiling (does not advance the simulation)
     rows_per_wave, tail_rpw1, tail_rows1, tile_order, waves = dom.stage_tiling(1)
-    rows2, tail_rpw2, tail_rows2, _, waves2 = dom.stage_tiling(2)
+    rows2, tail_rpw2, tail_rows2, dom_order2, waves2 = dom.stage_tiling(2)
 
     dom.step(a.warmup)
     torch.cuda.synchronize()
@@ -258,8 +258,10 @@ def bench_single(a, np, torch):
     gbs = bytes_dom / (ms_dom * 1e-3) / 1e9
     slots_dom = VALU_SLOTS_PER_CELL[dominant] * cells
     achieved = slots_dom / (ms_dom * 1e-3) / 1e12
+    # the byte counters were taken at tile order 0
     traffic = measured_traffic(f"stage{dominant}", *((rows_per_wave, tail_rpw1, tail_rows1) if dominant == 1
-                                                     else (rows2, tail_rpw2, tail_rows2)))
+                                                     else (rows2, tail_rpw2, tail_rows2))) \
+        if (tile_order if dominant == 1 else dom_order2) == 0 else None
 
     value = cells * a.steps / el
     out = {
@@ -281,7 +283,8 @@ def bench_single(a, np, torch):
             "boundaries": "nested (M2 tide, hourly snapshots) on all sides", "friction": "linear r=3e-3 m/s",
             "wind_stress_Nm2": 0.1, "courant": wl.courant, "dt_s": dt_next,
             "rows_per_wave": [rows_per_wave, rows2], "tail_rows_per_wave": [tail_rpw1, tail_rpw2],
-            "tail_rows": [tail_rows1, tail_rows2], "tile_order": tile_order, "waves_per_stage": [waves, waves2],
+            "tail_rows": [tail_rows1, tail_rows2], "tile_order": [tile_order, dom_order2],
+            "waves_per_stage": [waves, waves2],
             "tiling": "measured per stage kernel before the timed region (swe_autotune_tiling)",
         },
         "roofline": {
@@ -401,7 +404,7 @@ def bench_sweep(a, np, torch):
         dom.stage_times(reset=True)
         dom.step(a.sweep_steps)
         ms1, ms2, _ = dom.stage_times(reset=True)
-        rows = [dom.stage_tiling(1)[:3], dom.stage_tiling(2)[:3]]
+        rows = [dom.stage_tiling(1)[:4], dom.stage_tiling(2)[:4]]
         e, _, _, _, _ = dom.read_state()
         finite = bool(np.isfinite(e).all())
         dom.close()

@@ -888,8 +888,9 @@ void tail_candidates(const swe_domain *d, int stage, int by, std::vector<Tiling>
 
 // Time one stage kernel over candidate tilings and return the fastest: first
 // one band height for the whole domain (2 .. 64 rows), then the tails of
-// tail_candidates around the best height and the next two taller ones.  A
-// candidate replaces the incumbent only when it is more than 1 % faster.
+// tail_candidates around the best height and the next two taller ones, then
+// the other tile numberings of the winner.  A candidate replaces the
+// incumbent only when it is more than 1 % faster.
 int sweep_stage(swe_domain *d, int stage, Tiling *best_T)
 {
     const int nx = d->p.nx, ny = d->p.ny;
@@ -912,6 +913,17 @@ int sweep_stage(swe_domain *d, int stage, Tiling *best_T)
         float ms = 0.f;
         if ((he = tm.time(d, stage, tails[k], &ms)) != hipSuccess) break;
         if (ms < best_ms * 0.99f) { best_ms = ms; best = tails[k]; }
+    }
+    // the tile numbering of the winner: row-band-major keeps the rows that
+    // the resident waves touch close together (fewer pages in flight on
+    // large domains); without per-XCD grouping as a control
+    const Tiling won = best;
+    for (int order = 1; order <= 3 && he == hipSuccess; ++order) {
+        Tiling T = won;
+        T.order = order;
+        float ms = 0.f;
+        if ((he = tm.time(d, stage, T, &ms)) != hipSuccess) break;
+        if (ms < best_ms * 0.99f) { best_ms = ms; best = T; }
     }
     if (he != hipSuccess) return hip_fail(he, "tiling sweep");
     *best_T = best;

@@ -133,6 +133,7 @@ def error_vs_oracle(wl, ref, t_ref, steps, np, compensated=False):
     land cells excluded."""
     from paper_1912_02457_amd import Domain
     dom = Domain.from_workload(wl, device="cuda:0", compensated_state=compensated)
+    dom.autotune()  # the tilings the timed region uses
     dom.step(steps)
     e, u, v, t, _ = dom.read_state()
     dom.close()

@@ -243,6 +243,8 @@ def test_full_size_first_steps(which):
     rep = d.read_state()
     d.close()
     d = _dom(wl)
+    d.autotune()  # the tilings bench.py times (tails, tile order) as the tuner picks them
+    _say("tuned tilings", d.stage_tiling(1), d.stage_tiling(2))
     d.step(3)
     own = d.read_state()
     d.close()
@@ -467,7 +469,8 @@ def test_max_size_domain_tiling_invariant_and_conserving():
     """A 16384 x 16384 domain (268 M cells, 1 GiB per state plane, the
     32-bit byte offsets near their range): finite, mass conserved by the
     float64 diagnostic to float32 rounding, the CFL step of the initial state,
-    and bitwise the same under two tilings."""
+    and bitwise the same under three tilings (one with row-band-major tile
+    numbering and tails of short bands, as the tuner picks at this size)."""
     import torch
     N = 16384
     z = np.zeros((N, N), np.float32)
@@ -479,14 +482,18 @@ def test_max_size_domain_tiling_invariant_and_conserving():
     del z
     _say("max size init")
     outs = []
-    for by in (5, 16):
+    for by in (5, 16, (48, 3, 500, 1, 24, 2, 300)):
         d = _dom(wl)
         m0, _ = d.diagnostics()
         e = torch.empty((N, N), dtype=torch.float32, device="cuda:0")
         u, v = torch.empty_like(e), torch.empty_like(e)
         _, dt0 = d.read_state_into(e, u, v)
         assert dt0 == pytest.approx(0.45 * 0.25 * 1000.0 / np.sqrt(9.81 * (100.0 + float(bump.max()))), rel=1e-5)
-        d.set_tiling(by)
+        if isinstance(by, tuple):
+            d.set_stage_tiling(1, *by[0:3], order=by[3])
+            d.set_stage_tiling(2, *by[4:7], order=by[3])
+        else:
+            d.set_tiling(by)
         d.step(6)
         m1, _ = d.diagnostics()
         d.read_state_into(e, u, v)
@@ -495,5 +502,6 @@ def test_max_size_domain_tiling_invariant_and_conserving():
         outs.append((e, u, v))
         d.close()
         _say(f"max size by={by} mass drift {abs(m1 - m0) / m0:.2e}")
-    for a, b in zip(outs[0], outs[1]):
-        assert bool(torch.equal(a, b))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert bool(torch.equal(a, b))

@@ -375,6 +375,9 @@ def bench_compensated(a, np, torch, wl, full_value):
 # dt = 1600/N s, i.e. N steps): context for the size sweep, other hardware.
 PAPER_P100_TOTAL_S = {512: 0.169710, 1024: 1.170814, 2048: 9.133564, 4096: 72.832028,
                       8192: 582.599290, 16384: 4695.904546}
+# ... and the time to download the state (eta, hu, hv) to the host, same table
+PAPER_P100_DOWNLOAD_S = {512: 0.000929, 1024: 0.002773, 2048: 0.019642, 4096: 0.077541,
+                         8192: 0.305405, 16384: 1.218880}
 
 
 def bench_sweep(a, np, torch):
@@ -406,8 +409,15 @@ def bench_sweep(a, np, torch):
         dom.step(a.sweep_steps)
         ms1, ms2, _ = dom.stage_times(reset=True)
         rows = [dom.stage_tiling(1)[:4], dom.stage_tiling(2)[:4]]
-        e, _, _, _, _ = dom.read_state()
-        finite = bool(np.isfinite(e).all())
+        # state download into pinned host memory (the paper's download time)
+        host = [torch.empty((N, N), dtype=torch.float32, pin_memory=True) for _ in range(3)]
+        dl = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            dom.read_state_into(*host)
+            dl.append(time.perf_counter() - t1)
+        finite = bool(torch.isfinite(host[0]).all())
+        del host
         dom.close()
         cells = N * N
         v = cells * a.sweep_steps / el
@@ -418,13 +428,16 @@ def bench_sweep(a, np, torch):
                     "stage1_ms": ms1, "stage2_ms": ms2, "rows_per_wave": rows,
                     "hbm_frac_stage1": gbs1 / HBM_PEAK_GBS, "hbm_frac_stage2": gbs2 / HBM_PEAK_GBS,
                     "paper_run_s": paper_run, "paper_p100_total_s": PAPER_P100_TOTAL_S.get(N),
+                    "download_s": min(dl), "download_gb_s": 12.0 * cells / min(dl) / 1e9,
+                    "paper_p100_download_s": PAPER_P100_DOWNLOAD_S.get(N),
                     "state_finite": finite, "input_generation_s": t_gen})
         _progress(f"sweep {N}^2: {v:.3e} cell-updates/s")
         N *= 2
     return {"workload": "grid-convergence case (peaks bathymetry, cosine bump, pole latitude/north, walls), N x N",
             "steps": a.sweep_steps, "sizes": out,
             "note": "paper_run_s = N steps (1600 s at dt = 1600/N) at the measured rate; "
-                    "paper_p100_total_s is the paper's Tesla P100 total (context, other hardware)"}
+                    "paper_p100_total_s is the paper's Tesla P100 total (context, other hardware); "
+                    "download_s = best of 3 copies of eta, hu, hv into pinned host memory (swe_read_state)"}
 
 
 def _member(k):

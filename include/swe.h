@@ -333,7 +333,10 @@ void swe_ensemble_destroy(swe_ensemble *e);
  * swe_workspace_bytes of their domain) fits in the arena and an active slot
  * is free.  Each request's last step is clamped so that it ends exactly at
  * its horizon (the run-to-time rule of the scheme); a request's result is
- * bitwise the one it gets when run alone.  swe_server_submit may be called
+ * bitwise the one it gets when run alone.  The active set is of one kind
+ * (params.north_projection and params.compensated_state): a waiting request
+ * of another kind stays at the head of the queue, and the ones behind it
+ * wait too, until the active set has drained.  swe_server_submit may be called
  * from another thread while a tick runs; no other calls on one server may
  * overlap. */
 typedef struct swe_server swe_server;

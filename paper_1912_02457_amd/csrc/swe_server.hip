@@ -262,6 +262,16 @@ int admit(swe_server *s)
     while ((int)s->active.size() < s->max_active) {
         std::unique_ptr<Pending> q = pop_pending(s);
         if (!q) break;
+        // one ensemble launch runs one kernel variant: a request of another
+        // kind (north-vector projection, compensated state) than the active
+        // set waits at the head of the queue until the active set has drained
+        if (!s->active.empty()) {
+            const swe_params &a = s->active.front().dom->p, &b = q->r.params;
+            if (a.north_projection != b.north_projection || a.compensated_state != b.compensated_state) {
+                push_back_front(s, std::move(q));
+                break;
+            }
+        }
         size_t off;
         if (!s->arena.alloc(q->bytes, &off)) {
             if (s->active.empty()) return refuse_head(s, std::move(q));  // could never start

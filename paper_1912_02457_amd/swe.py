@@ -463,11 +463,11 @@ class Ensemble:
             pass
 
 
-def params_of(wl, north_projection=False) -> Params:
+def params_of(wl, north_projection=False, compensated_state=False) -> Params:
     return make_params(wl.nx, wl.ny, wl.dx, wl.dy, g=wl.g, courant=wl.courant, theta=wl.theta,
                        kappa=wl.kappa, bc=wl.bc, friction=wl.friction, friction_coeff=wl.friction_coeff,
                        rho_w=wl.rho_w, frs_width=wl.frs_width, frs_d0=wl.frs_d0,
-                       north_projection=north_projection)
+                       north_projection=north_projection, compensated_state=compensated_state)
 
 
 class Server:
@@ -491,12 +491,13 @@ class Server:
         self._h = h
         self._out = {}  # id -> host result arrays, alive until polled
 
-    def submit(self, wl, horizon: float, req_id: int, *, keep_result: bool = True):
+    def submit(self, wl, horizon: float, req_id: int, *, keep_result: bool = True, north_projection: bool = False,
+               compensated_state: bool = False):
         """Queue workload ``wl`` to be advanced to simulated time ``horizon``."""
         ny, nx = wl.ny, wl.nx
         r = Request()
         r.id = int(req_id)
-        r.params = params_of(wl)
+        r.params = params_of(wl, north_projection=north_projection, compensated_state=compensated_state)
         r.horizon = float(horizon)
         Hc = _f32(wl.Hc, (ny + 1, nx + 1))
         f = _f32(wl.f, (ny, nx))

@@ -158,3 +158,33 @@ def test_refused_request_is_reported_and_others_complete():
     assert done[2]["status"] == -1 and done[2]["steps"] == 0
     assert done[1]["status"] == 0 and done[1]["t"] == 200.0
     assert done[3]["status"] == 0 and done[3]["t"] == 100.0
+
+
+def test_mixed_kinds_are_served_in_turn():
+    """Requests with the compensated state or the literal north projection
+    run other kernel variants than the plain ones, so one batch holds one
+    kind: a stream that alternates kinds still completes every request,
+    each bitwise equal to its standalone run of the same kind, and never
+    mixes kinds in the active set."""
+    from paper_1912_02457_amd import Domain, Server
+    kinds = [dict(), dict(compensated_state=True), dict(), dict(north_projection=True), dict(compensated_state=True),
+             dict()]
+    wls = [(config5_member(120 + 30 * k, 90 + 10 * k, 0), 300.0 + 40.0 * k) for k in range(len(kinds))]
+    with Server(1 << 30, max_active=8, steps_per_tick=16, device="cuda:0") as srv:
+        for k, ((wl, h), kw) in enumerate(zip(wls, kinds)):
+            srv.submit(wl, h, req_id=k, **kw)
+        done = _drain(srv)
+        st = srv.stats()
+    assert sorted(c["id"] for c in done) == list(range(len(kinds)))
+    assert st["completed"] == len(kinds) and st["arena_used"] == 0
+    by_id = {c["id"]: c for c in done}
+    for k, ((wl, h), kw) in enumerate(zip(wls, kinds)):
+        c = by_id[k]
+        assert c["status"] == 0
+        d = Domain.from_workload(wl, device="cuda:0", **kw)
+        n = d.run_until(h)
+        e, u, v, t, _ = d.read_state()
+        d.close()
+        assert c["t"] == t and c["steps"] == n
+        for a, b in zip(c["state"], (e, u, v)):
+            assert np.array_equal(a, b), f"request {k} ({kw}) differs from its standalone run"

@@ -220,8 +220,9 @@ int swe_diagnostics(swe_domain *d, double *mass, double *energy);
 int swe_status(swe_domain *d);
 
 /* Measures both stage kernels of this domain for rows per tile in {2..64}
- * and, around the fastest, for tails of 1-4-row bands (swe_set_stage_tiling;
- * a few launches each) and keeps the fastest tiling per stage.  The state and the
+ * and, around the fastest, for tails of 1-4-row bands (swe_set_stage_tiling),
+ * then the winner under the other tile orders (a few launches each), and
+ * keeps the fastest tiling per stage.  The state and the
  * control block are saved to host memory first and restored afterwards, so
  * the simulation does not advance.  *rows_per_wave gets stage 1's choice
  * (may be NULL; swe_get_tiling reports each stage).  Synchronises.  Errors:
@@ -255,8 +256,9 @@ int swe_set_stage_tiling(swe_domain *d, int32_t stage, int32_t rows_per_wave, in
                          int32_t tail_rows, int32_t order);
 
 /* Every tiling swe_autotune_tiling may time for stage kernel `stage` on this
- * domain (the one-height tilings, then the tails tried around each height),
- * as triples (rows_per_wave, tail_rows_per_wave, tail_rows) in the form of
+ * domain (the one-height tilings, then the tails tried around each height;
+ * the tuner also times the winner under the four tile orders, which are not
+ * listed), as triples (rows_per_wave, tail_rows_per_wave, tail_rows) in the form of
  * swe_get_stage_tiling, into out[3 * max_tilings] (caller-owned host array;
  * NULL when max_tilings is 0).  *n_tilings gets the total count, which may
  * exceed max_tilings (then only the first max_tilings are written).  Lets a

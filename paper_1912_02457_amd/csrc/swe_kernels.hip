@@ -402,26 +402,38 @@ __device__ __forceinline__ void w10_stress(const Dom &d, const TileCtx &c, float
     sy = k * W[1];
 }
 
-// Flow relaxation (eq. frs) of one output cell, split so that its loads are
-// issued at the start of the row and consumed at the end: the nearest nested
-// side within the zone (ties W, E, S, N), its weight alpha = 1 - tanh(d/d0)
-// and the two boundary snapshots around the stage time.
+// Flow relaxation (eq. frs) of one output cell: whether it lies in a zone,
+// the nearest nested side within the zone (ties W, E, S, N), its weight
+// alpha = 1 - tanh(d/d0) and the two boundary snapshots around the stage
+// time.  The row loop only tests the zone at the start of a row; the loads
+// are issued where the update uses them (held across the row, they raised
+// the register count of the whole stage-2 kernel to three waves per SIMD).
 struct FrsPre {
     bool zone;
     float al;
     float a[3], b[3];
 };
 
+// nearest nested side of cell (i, o) (ties W, E, S, N) and its distance in
+// cells; best = -1 without nested sides
+__device__ __forceinline__ void frs_side(const Dom &d, int i, int o, int &best, int &dd)
+{
+    const int nx = d.nx, ny = d.ny;
+    int dist[4] = {i, nx - 1 - i, o, ny - 1 - o};
+    best = -1;
+    dd = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (d.bc[k] == BC_NESTED && (best < 0 || dist[k] < dd)) { best = k; dd = dist[k]; }
+}
+
 __device__ __forceinline__ FrsPre frs_prefetch(const Dom &d, const TileCtx &c)
 {
     FrsPre f;
     const int nx = d.nx, ny = d.ny, i = c.i, o = c.o;
-    int dist[4] = {i, nx - 1 - i, o, ny - 1 - o};
     int idxs[4] = {o, ny + o, 2 * ny + i, 2 * ny + nx + i};
-    int best = -1, dd = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if (d.bc[k] == BC_NESTED && (best < 0 || dist[k] < dd)) { best = k; dd = dist[k]; }
+    int best, dd;
+    frs_side(d, i, o, best, dd);
     f.zone = c.out_lane && best >= 0 && dd < d.frs_w;
     f.al = 0.f;
     f.a[0] = f.a[1] = f.a[2] = f.b[0] = f.b[1] = f.b[2] = 0.f;
@@ -542,11 +554,15 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
             vn = 0.5f * (v0 + (A.v + dt * Mv)) * den;
         }
         if (FRS && fp.zone) {
-            const float al = fp.al;
+            // the boundary values are loaded here, where they are used, not
+            // at the start of the row: held across the row they would raise
+            // the register count of every tile's kernel
+            const FrsPre fl = frs_prefetch(d, c);
+            const float al = fl.al;
             const double t = c.bs;
             float ex[3];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) ex[q] = (float)((1.0 - t) * (double)fp.a[q] + t * (double)fp.b[q]);
+            for (int q = 0; q < 3; ++q) ex[q] = (float)((1.0 - t) * (double)fl.a[q] + t * (double)fl.b[q]);
             if (COMP) {
                 en = two_sum(en, le + al * ((ex[0] - en) - le), le);
                 un = two_sum(un, lu + al * ((ex[1] - un) - lu), lu);
@@ -739,7 +755,11 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
         }
         FrsPre fp;
         fp.zone = false;
-        if (STAGE == 2 && FRS) fp = frs_prefetch(d, c);
+        if (STAGE == 2 && FRS) {
+            int best, dd;
+            frs_side(d, c.i, c.o, best, dd);
+            fp.zone = c.out_lane && best >= 0 && dd < d.frs_w;
+        }
         load(C, k);
         y_diff(C, B, d);
         float us, vs;

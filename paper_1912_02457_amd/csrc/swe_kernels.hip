@@ -457,7 +457,7 @@ __device__ __forceinline__ FrsPre frs_prefetch(const Dom &d, const TileCtx &c)
 // Every lane takes part in the cross-lane exchanges; only output lanes store.
 template <int STAGE, bool PROJ, bool FRS, bool W10, bool COMP>
 __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 &Gn, const TileCtx &c,
-                                           float e0, float u0, float v0, const Lo &lo, const FrsPre &fp,
+                                           float e0, float u0, float v0, bool lo_ok, const FrsPre &fp,
                                            const Dom &d, float &wmax_loc, int &bad)
 {
     const float th = d.theta;
@@ -509,6 +509,19 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
     const uint32_t oo = (uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i;
     const float dt = c.dt;
     float S = friction_coeff(d, A.ri, A.u, A.v);
+    // compensated: the stored rounding errors of the cell, loaded where they
+    // are used (held across the row they would raise the register count)
+    Lo lo{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (COMP && lo_ok) {
+        lo.e0 = ld(d.eta_lo, oo);
+        lo.u0 = ld(d.hu_lo, oo);
+        lo.v0 = ld(d.hv_lo, oo);
+        if (STAGE == 2) {
+            lo.e1 = ld(d.eta1_lo, oo);
+            lo.u1 = ld(d.hu1_lo, oo);
+            lo.v1 = ld(d.hv1_lo, oo);
+        }
+    }
     if (STAGE == 1) {
         float den = rcp(1.f + dt * S);
         if (COMP) {
@@ -735,23 +748,11 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
     auto step = [&](Row &A, Row &B, Row &C, int k) {
         c.o = k - 2;
         float e0 = 0.f, u0 = 0.f, v0 = 0.f;
-        Lo lo{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (STAGE == 2 && (!GHOST || c.out_lane)) {
             const uint32_t oq = (uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i;
             e0 = ld(d.eta, oq);
             u0 = ld(d.hu, oq);
             v0 = ld(d.hv, oq);
-        }
-        if (COMP && (!GHOST || c.out_lane)) {
-            const uint32_t oq = (uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i;
-            lo.e0 = ld(d.eta_lo, oq);
-            lo.u0 = ld(d.hu_lo, oq);
-            lo.v0 = ld(d.hv_lo, oq);
-            if (STAGE == 2) {
-                lo.e1 = ld(d.eta1_lo, oq);
-                lo.u1 = ld(d.hu1_lo, oq);
-                lo.v1 = ld(d.hv1_lo, oq);
-            }
         }
         FrsPre fp;
         fp.zone = false;
@@ -767,7 +768,7 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
         F3 Gn = y_flux(A, B, us, vs, d);
         // a row whose output cells are all land has nothing to update
         if (__ballot(c.out_lane && !A.land) != 0)
-            finish_row<STAGE, PROJ, FRS, W10, COMP>(A, Gs, Gn, c, e0, u0, v0, lo, fp, d, wmax_loc, bad);
+            finish_row<STAGE, PROJ, FRS, W10, COMP>(A, Gs, Gn, c, e0, u0, v0, !GHOST || c.out_lane, fp, d, wmax_loc, bad);
         Gs = Gn;
     };
     for (int k = y0 + 2;;) {

@@ -937,7 +937,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Ti
 // Every member has its own parameters, time, dt slot and CFL accumulator.
 // ---------------------------------------------------------------------------
 template <int STAGE, bool PROJ, bool W10, bool COMP>
-__global__ __launch_bounds__(kWave * kWavesPerBlock) void ensemble_kernel(const EnsMember *__restrict__ mem,
+__global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu((COMP || PROJ || W10) ? 1 : 4)))
+void ensemble_kernel(const EnsMember *__restrict__ mem,
                                                                          const EnsItem *__restrict__ items,
                                                                          EnsCtrl *ec, int parity, int chunk)
 {

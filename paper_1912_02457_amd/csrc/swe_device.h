@@ -200,7 +200,7 @@ __host__ __device__ inline int block_tile(const Tiling &T, int b, int wid)
 
 // Strip and rows [y0, y1) of a tile (0 <= tile < T.ntiles).  Within the head
 // and within the tail, tiles are numbered strip-major (order bit 0 clear) or
-// row-band-major.
+// row-band-major, with the strips in the order 0, last, 1, 2, ...
 __host__ __device__ inline void tile_place(const Tiling &T, int tile, int ny, int &strip, int &y0, int &y1)
 {
     int t = tile, nb = T.nrb1, by = T.by, base = 0;
@@ -213,6 +213,9 @@ __host__ __device__ inline void tile_place(const Tiling &T, int tile, int ny, in
     int rb;
     if (T.order & 1) { rb = t / T.nstrips; strip = t - rb * T.nstrips; }
     else { strip = t / nb; rb = t - strip * nb; }
+    // the two edge strips (ghost columns, relaxation zones: the slowest
+    // tiles) come first, so that they are not left for the end of a launch
+    strip = strip == 0 ? 0 : (strip == 1 ? T.nstrips - 1 : strip - 1);
     y0 = base + rb * by;
     y1 = y0 + by < ny ? y0 + by : ny;
 }

@@ -38,7 +38,9 @@ extern "C" {
 #define SWE_E_ARG (-1)      /* invalid size, parameter, pointer or non-finite input */
 #define SWE_E_NOMEM (-2)    /* caller workspace too small */
 #define SWE_E_HIP (-3)      /* HIP runtime error; message in swe_last_error() */
-#define SWE_E_UNSTABLE (-4) /* a step produced a non-finite state (flag raised on the device) */
+#define SWE_E_UNSTABLE (-4) /* a non-finite state, or a water depth eta + Hbar below -kappa in a
+                               non-land cell, was seen by the CFL reduction (a flag raised on the
+                               device after a step, swe_set_state or init; cleared by swe_set_state) */
 #define SWE_E_STATE (-5)    /* call out of order (e.g. nested sides without boundary data) */
 
 /* boundary kinds, per side in the order West, East, South, North */
@@ -170,8 +172,13 @@ int swe_set_stress_field(swe_domain *d, int32_t n_times, int32_t nx_w, int32_t n
 /* Advance n_steps SSP-RK2 steps (eq. rk2_semiimp with the spatial operator of
  * eq. sw_semidiscrete), each with the dt of eq. cfl computed on the device
  * from the state at the start of the step.  Asynchronous: no host
- * synchronisation.  Uses a captured HIP graph of the two stage kernels once
- * the step count repeats.  Errors: SWE_E_ARG (n_steps < 0), SWE_E_STATE
+ * synchronisation.  Steps run as replays of captured HIP graphs of the two
+ * stage kernels: chunks of 16 steps, then the remaining n_steps mod 16 as
+ * one graph of that length; each graph is captured (and instantiated) on
+ * its first use at a given step parity and kept until the domain is
+ * destroyed or its tiling or forcing changes, so a caller that times
+ * repeated calls should make one untimed call of the same length at the
+ * same parity first.  Errors: SWE_E_ARG (n_steps < 0), SWE_E_STATE
  * (nested side without boundary data), SWE_E_HIP. */
 int swe_step(swe_domain *d, int32_t n_steps);
 
@@ -215,8 +222,9 @@ int swe_set_state(swe_domain *d, const float *eta, const float *hu, const float 
  * four corner depths.  Deterministic order.  Synchronises. */
 int swe_diagnostics(swe_domain *d, double *mass, double *energy);
 
-/* SWE_OK, or SWE_E_UNSTABLE once a step produced a non-finite value.
- * Synchronises. */
+/* SWE_OK, or SWE_E_UNSTABLE once a step (or the state given at init or to
+ * swe_set_state) had a non-finite value or a water depth below -kappa in a
+ * non-land cell; swe_last_error() says which.  Synchronises. */
 int swe_status(swe_domain *d);
 
 /* Measures both stage kernels of this domain for rows per tile in {2..64}
@@ -317,8 +325,10 @@ int swe_ensemble_stage_times(swe_ensemble *e, double *ms_stage1, double *ms_stag
                              int32_t reset);
 
 /* on = 1 (default): swe_ensemble_step replays captured HIP graphs of 16
- * steps; on = 0: every stage is launched directly (no capture cost, for
- * ensembles that live only a few steps, as in the serving loop). */
+ * steps and one of the remaining n_steps mod 16 steps (each captured on its
+ * first use at a given step parity, as in swe_step); on = 0: every stage is
+ * launched directly (no capture cost, for ensembles that live only a few
+ * steps, as in the serving loop). */
 int swe_ensemble_use_graphs(swe_ensemble *e, int32_t on);
 
 /* Releases the ensemble; the members return to their own streams. */

@@ -84,6 +84,8 @@ def lib():
         L.or_diagnostics.restype = None
         L.or_diagnostics.argtypes = [P, S, _D, _D, _D, _D, _D]
         L.or_num_threads.restype = C.c_int
+        L.or_set_num_threads.restype = None
+        L.or_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -118,6 +120,11 @@ def cu_flux(L, R, Hf, g=9.81, kappa=1e-3) -> np.ndarray:
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's loops over rows (results do not depend on it)."""
+    lib().or_set_num_threads(int(n))
 
 
 def resample_boundary(data, nx, ny, n_x, n_y):

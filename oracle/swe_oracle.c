@@ -33,6 +33,17 @@
 
 #define NG 2 /* ghost layers: a face value needs the slope, which needs a neighbour */
 
+/* threads of the parallel loops over rows (timing of the oracle only; the
+ * rows are independent, so the result does not depend on it) */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int or_num_threads(void)
 {
 #ifdef _OPENMP

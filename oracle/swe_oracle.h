@@ -110,6 +110,7 @@ void or_diagnostics(const or_params *p, const or_static *s, const double *eta, c
                     const double *hv, double *mass, double *energy);
 
 int or_num_threads(void);
+void or_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

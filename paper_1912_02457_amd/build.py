@@ -1,16 +1,24 @@
-"""Builds the gfx950 HIP library ``lib/libswe_hip.so`` in-tree with hipcc."""
+"""Builds the gfx950 HIP library ``lib/libswe_hip.so`` in-tree with hipcc.
+
+Each source is compiled to an object of its own (in parallel), then the
+objects are linked into the shared library; kernels are launched only from
+the translation unit that defines them, so no relocatable device code is
+needed.
+"""
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["csrc/swe_kernels.hip", "csrc/swe_api.hip", "csrc/swe_ensemble.hip", "csrc/swe_server.hip",
            "csrc/swe_preprocess.hip"]
 LIB = os.path.join(HERE, "lib", "libswe_hip.so")
+OBJ_DIR = os.path.join(HERE, "lib", "obj")
 ARCH = os.environ.get("SWE_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions in any generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # fuse a*b+c only within one expression: every inlined copy of the same
@@ -20,15 +28,29 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(os.path.dirname(LIB), exist_ok=True)
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, "-o", tmp, *[os.path.join(HERE, s) for s in SOURCES]]
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJ_DIR, os.path.basename(src).replace(".hip", ".o"))
+    cmd = ["hipcc", *HIPCC_FLAGS, "-c", "-o", obj, os.path.join(HERE, src)]
     if verbose:
-        print(" ".join(cmd))
+        print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed:\n{r.stderr[-4000:]}")
+        raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr[-4000:]}")
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc link failed:\n{r.stderr[-4000:]}")
     os.replace(tmp, LIB)
     return LIB
 

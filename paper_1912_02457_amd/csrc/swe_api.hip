@@ -622,12 +622,15 @@ int swe_step(swe_domain *d, int32_t n_steps)
     if (n_steps < 0) return fail(SWE_E_ARG, "n_steps < 0");
     int left = n_steps;
     if (!d->timing) {
-        while (left >= kGraphChunk) {
+        // whole chunks, then the remainder, each through a graph captured on
+        // its first use and kept per (steps, parity): at most 2 x 16 graphs
+        while (left > 0) {
+            const int n = left >= kGraphChunk ? kGraphChunk : left;
             hipGraphExec_t g;
-            if ((rc = get_graph(d, kGraphChunk, d->parity, &g))) return rc;
+            if ((rc = get_graph(d, n, d->parity, &g))) return rc;
             HIP_TRY(hipGraphLaunch(g, d->stream));
-            d->parity = (d->parity + kGraphChunk) & 1;
-            left -= kGraphChunk;
+            d->parity = (d->parity + n) & 1;
+            left -= n;
         }
     }
     for (; left > 0; --left) {
@@ -680,7 +683,7 @@ int swe_run_until(swe_domain *d, double t_end, int64_t *steps_taken)
     }
     if ((rc = read_ctrl(d, &c))) return rc;
     if (steps_taken) *steps_taken = c.steps - s0;
-    if (c.flags) return fail(SWE_E_UNSTABLE, "non-finite state");
+    if (c.flags) return fail(SWE_E_UNSTABLE, flag_message(c.flags));
     return SWE_OK;
 }
 
@@ -711,7 +714,7 @@ int swe_read_state(swe_domain *d, float *eta, float *hu, float *hv, double *t, d
         if (staged[k]) std::memcpy(dst[k], d->pinned_state + k * plane, plane * sizeof(float));
     if (t) *t = c.t[d->parity];
     if (dt_next) *dt_next = ctrl_next_dt(c, d->parity, d->dom.courant_q, d->dom.dt_interval);
-    if (c.flags) return fail(SWE_E_UNSTABLE, "non-finite state");
+    if (c.flags) return fail(SWE_E_UNSTABLE, flag_message(c.flags));
     return SWE_OK;
 }
 
@@ -768,7 +771,7 @@ int swe_status(swe_domain *d)
     Ctrl c;
     int rc = read_ctrl(d, &c);
     if (rc) return rc;
-    return c.flags ? fail(SWE_E_UNSTABLE, "non-finite state") : SWE_OK;
+    return c.flags ? fail(SWE_E_UNSTABLE, flag_message(c.flags)) : SWE_OK;
 }
 
 int swe_set_tiling(swe_domain *d, int32_t rows_per_wave, int32_t order)

@@ -35,7 +35,7 @@ constexpr int kCflStride = 32;  // uint32 words between slots (128 B)
 // while the next step's slots are being produced.
 struct Ctrl {
     double t[2];         // time at the start of the step of each parity
-    uint32_t flags;      // bit 0: non-finite state produced
+    uint32_t flags;      // bit 0: non-finite state produced; bit 1: water depth below -kappa
     float dt_last;       // dt of the last step taken
     int64_t steps;       // steps taken (no-op steps past t_end excluded)
     double t_end;        // > 0: clamp steps to end exactly at t_end, skip steps after it
@@ -47,6 +47,13 @@ struct Ctrl {
     // max over non-land cells of max((|u|+c)/dx, (|v|+c)/dy) as float bits, per parity
     uint32_t wslot[2][kCflSlots][kCflStride];
 };
+
+// host-side text of the error flags
+inline const char *flag_message(uint32_t flags)
+{
+    if ((flags & 3u) == 3u) return "non-finite state and water depth below -kappa";
+    return (flags & 2u) ? "water depth below -kappa (positivity lost)" : "non-finite state";
+}
 
 // host-side maximum over the slots of one parity
 inline float ctrl_wmax(const Ctrl &c, int parity)

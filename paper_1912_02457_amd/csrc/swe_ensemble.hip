@@ -257,12 +257,15 @@ int swe_ensemble_step(swe_ensemble *e, int32_t n_steps)
     if (e->broken) return set_error(SWE_E_STATE, "a member was destroyed before its ensemble");
     int left = n_steps, rc;
     if (!e->timing && e->use_graphs) {
-        while (left >= kEnsGraphChunk) {
+        // whole chunks, then the remainder, each through a graph captured on
+        // its first use and kept per (steps, parity)
+        while (left > 0) {
+            const int n = left >= kEnsGraphChunk ? kEnsGraphChunk : left;
             hipGraphExec_t g;
-            if ((rc = ens_graph(e, kEnsGraphChunk, e->parity, &g))) return rc;
+            if ((rc = ens_graph(e, n, e->parity, &g))) return rc;
             EHIP(hipGraphLaunch(g, e->stream));
-            e->parity = (e->parity + kEnsGraphChunk) & 1;
-            left -= kEnsGraphChunk;
+            e->parity = (e->parity + n) & 1;
+            left -= n;
         }
     }
     for (; left > 0; --left) {

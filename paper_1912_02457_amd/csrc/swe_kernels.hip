@@ -602,7 +602,10 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
         float cw = fsqrt(d.g * fmaxf(h, 0.f));
         float w = fmaxf((fabsf(un * ri) + cw) * d.rdx, (fabsf(vn * ri) + cw) * d.rdy);
         wmax_loc = store ? fmaxf(wmax_loc, w) : wmax_loc;
-        bad |= (store && !(isfinite(en) && isfinite(un) && isfinite(vn))) ? 1 : 0;
+        // bit 0: a non-finite state; bit 1: a water depth below -kappa (the
+        // scheme keeps h >= 0 under its CFL bound, so this means breakdown)
+        const int nonfin = (isfinite(en) && isfinite(un) && isfinite(vn)) ? 0 : 1;
+        bad |= store ? (nonfin | (h < -d.kappa ? 2 : 0)) : 0;
     }
 }
 
@@ -899,10 +902,10 @@ __device__ __forceinline__ void process_tile(const Dom &d, const Tiling &T, int 
 
     if (STAGE == 2) {
         wmax_loc = wave_max(wmax_loc);
-        unsigned long long anybad = __ballot(bad);
+        const uint32_t fl = (__ballot(bad & 1) ? 1u : 0u) | (__ballot(bad & 2) ? 2u : 0u);
         if (lane == 0) {
             atomicMax(&d.ctrl->wslot[parity ^ 1][tile & (kCflSlots - 1)][0], __float_as_uint(wmax_loc));
-            if (anybad) atomicOr(&d.ctrl->flags, 1u);
+            if (fl) atomicOr(&d.ctrl->flags, fl);
         }
     }
 }
@@ -990,15 +993,16 @@ __global__ void cfl_kernel(Dom d, int slot)
             float ri = rcp(desing(h, d));
             float c = fsqrt(d.g * fmaxf(h, 0.f));
             w = fmaxf((fabsf(u * ri) + c) * d.rdx, (fabsf(v * ri) + c) * d.rdy);
-            if (!(isfinite(e) && isfinite(u) && isfinite(v))) bad = 1;
+            if (!(isfinite(e) && isfinite(u) && isfinite(v))) bad |= 1;
+            if (h < -d.kappa) bad |= 2;
         }
     }
     w = wave_max(w);
-    unsigned long long anybad = __ballot(bad);
+    const uint32_t fl = (__ballot(bad & 1) ? 1u : 0u) | (__ballot(bad & 2) ? 2u : 0u);
     if ((threadIdx.x & (kWave - 1)) == 0) {
         int k = (blockIdx.x + blockIdx.y * gridDim.x + (threadIdx.x / kWave)) & (kCflSlots - 1);
         atomicMax(&d.ctrl->wslot[slot][k][0], __float_as_uint(w));
-        if (anybad) atomicOr(&d.ctrl->flags, 1u);
+        if (fl) atomicOr(&d.ctrl->flags, fl);
     }
 }
 

@@ -160,7 +160,7 @@ def _fp(a: Optional[np.ndarray]):
 def make_params(nx, ny, dx, dy, *, g=9.81, courant=0.45, theta=1.3, kappa=1e-3,
                 bc: Sequence[int] = (BC_WALL,) * 4, friction=FRICTION_NONE, friction_coeff=0.0,
                 rho_w=1025.0, frs_width=10, frs_d0=2.0, north_projection=False,
-                compensated_state=False) -> Params:
+                compensated_state=True) -> Params:
     p = Params()
     p.nx, p.ny, p.dx, p.dy, p.g = int(nx), int(ny), float(dx), float(dy), float(g)
     p.courant, p.theta, p.kappa = float(courant), float(theta), float(kappa)
@@ -211,7 +211,7 @@ class Domain:
         self._h = h
 
     @classmethod
-    def from_workload(cls, wl, *, north_projection=False, compensated_state=False, max_wind_times=None,
+    def from_workload(cls, wl, *, north_projection=False, compensated_state=True, max_wind_times=None,
                       max_bnd_times=None,
                       device=None, stream=None) -> "Domain":
         p = make_params(wl.nx, wl.ny, wl.dx, wl.dy, g=wl.g, courant=wl.courant, theta=wl.theta,
@@ -463,7 +463,7 @@ class Ensemble:
             pass
 
 
-def params_of(wl, north_projection=False, compensated_state=False) -> Params:
+def params_of(wl, north_projection=False, compensated_state=True) -> Params:
     return make_params(wl.nx, wl.ny, wl.dx, wl.dy, g=wl.g, courant=wl.courant, theta=wl.theta,
                        kappa=wl.kappa, bc=wl.bc, friction=wl.friction, friction_coeff=wl.friction_coeff,
                        rho_w=wl.rho_w, frs_width=wl.frs_width, frs_d0=wl.frs_d0,
@@ -492,7 +492,7 @@ class Server:
         self._out = {}  # id -> host result arrays, alive until polled
 
     def submit(self, wl, horizon: float, req_id: int, *, keep_result: bool = True, north_projection: bool = False,
-               compensated_state: bool = False):
+               compensated_state: bool = True):
         """Queue workload ``wl`` to be advanced to simulated time ``horizon``."""
         ny, nx = wl.ny, wl.nx
         r = Request()

@@ -28,9 +28,11 @@ def gpu():
     return torch
 
 
-def _dom(wl, **kw):
+def _dom(wl, comp=False, **kw):
+    """A domain with the float32 state of the paper unless comp is set (the
+    compensated state has tests of its own in test_gpu_compensated.py)."""
     from paper_1912_02457_amd import Domain
-    return Domain.from_workload(wl, device="cuda:0", **kw)
+    return Domain.from_workload(wl, device="cuda:0", compensated_state=comp, **kw)
 
 
 def _say(*a):
@@ -38,16 +40,16 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def run_both(wl, nsteps, proj=False):
+def run_both(wl, nsteps, proj=False, comp=False):
     """Oracle with its own CFL dt; GPU once replaying the oracle's dt sequence
     and once with its own on-device dt."""
     ref, t_ref, dts, k = O.Oracle(wl).run(nsteps=nsteps)
     assert k == nsteps
-    d = _dom(wl, north_projection=proj)
+    d = _dom(wl, comp=comp, north_projection=proj)
     d.step_dt(dts)
     rep = d.read_state()
     d.close()
-    d = _dom(wl, north_projection=proj)
+    d = _dom(wl, comp=comp, north_projection=proj)
     d.step(nsteps)
     own = d.read_state()
     d.close()
@@ -82,11 +84,12 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("comp", [False, True], ids=["f32state", "compensated"])
 @pytest.mark.parametrize("name,nx,ny,kw", CASES, ids=[c[0] for c in CASES])
-def test_random_cases(name, nx, ny, kw):
+def test_random_cases(name, nx, ny, kw, comp):
     wl = random_small(nx, ny, seed=zlib.crc32(name.encode()) % 1000, steps=30, **kw)
-    _say("case", name, nx, ny)
-    ref, t_ref, rep, own = run_both(wl, 30)
+    _say("case", name, nx, ny, "compensated" if comp else "float32 state")
+    ref, t_ref, rep, own = run_both(wl, 30, comp=comp)
     assert_parity(rep, ref, wl.land, label=f"{name} dt-replay")
     assert_parity(own, ref, wl.land, label=f"{name} own-dt")
     if wl.land is not None:
@@ -364,6 +367,29 @@ def test_unstable_flag_raised():
     with pytest.raises(SweError) as ei:
         d.read_state()
     assert ei.value.code == -4
+    d.close()
+
+
+def test_negative_depth_flag_raised():
+    """A water depth below -kappa in a wet cell (here handed in through
+    set_state; the scheme itself keeps h >= 0 under its CFL bound) raises the
+    device flag: SWE_E_UNSTABLE naming the depth, not a non-finite value; a
+    valid state handed in afterwards clears it."""
+    from paper_1912_02457_amd import SweError
+    wl = random_small(64, 32, seed=3)
+    d = _dom(wl)
+    Hbar = 0.25 * (wl.Hc[:-1, :-1] + wl.Hc[1:, :-1] + wl.Hc[:-1, 1:] + wl.Hc[1:, 1:])
+    eta = wl.eta.copy()
+    eta[10, 20] = -Hbar[10, 20] - 0.5
+    d.set_state(eta, wl.hu, wl.hv)
+    assert d.status() == -4
+    with pytest.raises(SweError) as ei:
+        d.read_state()
+    assert ei.value.code == -4 and "depth" in str(ei.value), str(ei.value)
+    d.set_state(wl.eta, wl.hu, wl.hv)
+    assert d.status() == 0
+    d.step(5)
+    d.read_state()
     d.close()
 
 

@@ -167,8 +167,9 @@ def test_mixed_kinds_are_served_in_turn():
     each bitwise equal to its standalone run of the same kind, and never
     mixes kinds in the active set."""
     from paper_1912_02457_amd import Domain, Server
-    kinds = [dict(), dict(compensated_state=True), dict(), dict(north_projection=True), dict(compensated_state=True),
-             dict()]
+    f32 = dict(compensated_state=False)
+    kinds = [f32, dict(compensated_state=True), f32, dict(north_projection=True), dict(compensated_state=True),
+             f32]
     wls = [(config5_member(120 + 30 * k, 90 + 10 * k, 0), 300.0 + 40.0 * k) for k in range(len(kinds))]
     with Server(1 << 30, max_active=8, steps_per_tick=16, device="cuda:0") as srv:
         for k, ((wl, h), kw) in enumerate(zip(wls, kinds)):

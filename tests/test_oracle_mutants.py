@@ -47,6 +47,21 @@ MUTANTS = {
                                         "    if (0) {"),
     "wind_samples_at_corners": ("double gx = (i + 0.5) * p->w10_nx / (double)p->nx - 0.5;",
                                 "double gx = (i + 0.5) * (p->w10_nx - 1) / (double)p->nx;"),
+    "energy_kinetic_unhalved": ("e += (0.5 * (hu[o] * hu[o] + hv[o] * hv[o]) / hs",
+                                "e += ((hu[o] * hu[o] + hv[o] * hv[o]) / hs"),
+    "energy_potential_unhalved": ("/ hs + 0.5 * p->g * eta[o] * eta[o]) * area;",
+                                  "/ hs + p->g * eta[o] * eta[o]) * area;"),
+    "energy_depth_not_desingularised": ("/ hs + 0.5 * p->g * eta[o] * eta[o]) * area;",
+                                        "/ h + 0.5 * p->g * eta[o] * eta[o]) * area;"),
+    "diagnostics_count_land": ("continue;\n            double h = eta[o] + cell_hbar(s, p->nx, i, j);\n"
+                               "            double hs = or_desing(h, p->kappa);\n            m +=",
+                               ";\n            double h = eta[o] + cell_hbar(s, p->nx, i, j);\n"
+                               "            double hs = or_desing(h, p->kappa);\n            m +="),
+    "mass_without_mean_depth": ("            m += h * area;", "            m += eta[o] * area;"),
+    "mass_one_corner_depth": ("double h = eta[o] + cell_hbar(s, p->nx, i, j);\n"
+                              "            double hs = or_desing(h, p->kappa);\n            m +=",
+                              "double h = eta[o] + s->Hc[(size_t)j * (p->nx + 1) + i];\n"
+                              "            double hs = or_desing(h, p->kappa);\n            m +="),
 }
 
 

@@ -281,6 +281,95 @@ def test_mass_conservation_closed_basin(wet_dry):
         assert np.array_equal(e[lm], s0[0][lm]) and np.array_equal(u[lm], s0[1][lm])
 
 
+def _plane_mean(a, b, c, x0, x1, y0, y1):
+    """Mean of the plane a + b x + c y over [x0, x1] x [y0, y1]: its value at
+    the rectangle's centroid."""
+    return a + b * 0.5 * (x0 + x1) + c * 0.5 * (y0 + y1)
+
+
+def test_diagnostics_mass_over_a_planar_bottom():
+    """Mass of the section "Mathematical formulation" (sum over water cells
+    of the depth eta + H times the cell area) for a lake at rest over a
+    planar bottom, where the piecewise bilinear bathymetry is that plane and
+    the integral over any rectangle is the plane's value at its centroid
+    times its area: the whole domain, and the domain less a rectangle of
+    land cells (land holds no water)."""
+    nx, ny, dx, dy = 23, 17, 700.0, 450.0
+    a, b, c, eta0 = 40.0, 3e-3, -2e-3, 0.37
+    X, Y = np.meshgrid(np.arange(nx + 1) * dx, np.arange(ny + 1) * dy)
+    Hc = a + b * X + c * Y
+    eta = np.full((ny, nx), eta0)
+    Lx, Ly = nx * dx, ny * dy
+    o = O.Oracle(make_wl(Hc, eta, dx=dx, dy=dy))
+    m, _ = o.diagnostics(o.initial_state())
+    want = (eta0 + _plane_mean(a, b, c, 0, Lx, 0, Ly)) * Lx * Ly
+    assert abs(m - want) <= 1e-13 * want
+    land = np.zeros((ny, nx), np.uint8)
+    i0, i1, j0, j1 = 4, 11, 9, 15
+    land[j0:j1, i0:i1] = 1
+    eta_l = eta.copy()
+    eta_l[land > 0] = 5.0  # what a land cell holds does not count
+    o = O.Oracle(make_wl(Hc, eta_l, land=land, dx=dx, dy=dy))
+    m, _ = o.diagnostics(o.initial_state())
+    blk = (eta0 + _plane_mean(a, b, c, i0 * dx, i1 * dx, j0 * dy, j1 * dy)) * (i1 - i0) * dx * (j1 - j0) * dy
+    assert abs(m - (want - blk)) <= 1e-13 * want
+
+
+def test_diagnostics_energy_closed_forms():
+    """Energy sum over water cells of (|hu|^2 / (2 h*) + g eta^2 / 2) times
+    the cell area (kinetic energy with the desingularised depth of eq.
+    desing_ours, potential energy of the free surface above the rest state):
+    a raised lake at rest has only the potential part, a uniform current on
+    a flat bottom only the kinetic part, a cell shallower than kappa divides
+    by h* (5 kappa / 8 at h = kappa / 2), and land cells count nothing."""
+    nx, ny, dx, dy = 12, 9, 300.0, 500.0
+    area = dx * dy
+    rng = np.random.default_rng(5)
+    Hc = 20.0 + 30.0 * rng.random((ny + 1, nx + 1))
+    eta0 = -0.42
+    o = O.Oracle(make_wl(Hc, np.full((ny, nx), eta0), dx=dx, dy=dy))
+    _, e = o.diagnostics(o.initial_state())
+    assert abs(e - 0.5 * G * eta0 ** 2 * nx * ny * area) <= 1e-13 * e
+    H, p, q = 35.0, 2.5, -1.5
+    o = O.Oracle(make_wl(np.full((ny + 1, nx + 1), H), np.zeros((ny, nx)), hu=np.full((ny, nx), p),
+                         hv=np.full((ny, nx), q), dx=dx, dy=dy))
+    _, e = o.diagnostics(o.initial_state())
+    assert abs(e - 0.5 * (p * p + q * q) / H * nx * ny * area) <= 1e-13 * e
+    kappa = 1e-3
+    eta = np.zeros((ny, nx))
+    eta[4, 6] = -H + 0.5 * kappa  # h = kappa / 2
+    hu = np.zeros((ny, nx))
+    hu[4, 6] = 1e-4
+    land = np.zeros((ny, nx), np.uint8)
+    land[2, 3] = 1
+    eta[2, 3], hu[2, 3] = 9.0, 7.0
+    o = O.Oracle(make_wl(np.full((ny + 1, nx + 1), H), eta, hu=hu, land=land, dx=dx, dy=dy, kappa=kappa))
+    _, e = o.diagnostics(o.initial_state())
+    want = (0.5 * 1e-4 ** 2 / (5.0 * kappa / 8.0) + 0.5 * G * (H - 0.5 * kappa) ** 2) * area
+    assert abs(e - want) <= 1e-13 * want
+
+
+def test_energy_does_not_grow_in_a_closed_basin():
+    """Without friction or forcing the shallow-water energy is conserved by
+    smooth flows and the upwind numerical diffusion can only remove it: in a
+    closed basin with varying depth and rotation the oracle's energy never
+    rises between checkpoints and ends below where it started, while the
+    mass stays fixed."""
+    wl = random_small(40, 30, seed=11, land_frac=0.1)
+    wl = wl.copy(Hc=wl.Hc.astype(np.float64), eta=wl.eta.astype(np.float64))
+    o = O.Oracle(wl)
+    st = o.initial_state()
+    m0, e0 = o.diagnostics(st)
+    t, prev = 0.0, e0
+    for _ in range(15):
+        st, t, _, _ = o.run(st, t, nsteps=20)
+        m, e = o.diagnostics(st)
+        assert e <= prev * (1.0 + 1e-13), (e, prev)
+        assert abs(m - m0) <= 1e-12 * abs(m0)
+        prev = e
+    assert prev < e0 * (1.0 - 1e-6)
+
+
 def _mirror_x(wl, flip_f):
     return wl.copy(Hc=wl.Hc[:, ::-1].copy(), eta=wl.eta[:, ::-1].copy(), hu=-wl.hu[:, ::-1],
                    hv=wl.hv[:, ::-1].copy(), f=(-1 if flip_f else 1) * wl.f[:, ::-1],

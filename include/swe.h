@@ -449,6 +449,23 @@ void swe_server_destroy(swe_server *s);
 int swe_reconstruct_bathymetry(int32_t nx, int32_t ny, const float *Hm, const uint8_t *land, int32_t iters,
                                float smooth, float *Hc, float *scratch, void *hip_stream);
 
+/* swe_reconstruct_bathymetry for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and the same result (bitwise), but the
+ * corner plane the rounds alternate with Hc is a device array of the
+ * library's own -- 16 MiB per GPU, reserved on every GPU the library is
+ * loaded on and held until the process ends -- so no scratch argument.
+ * The caller still passes Hm, land, Hc and the stream as above.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine);
+ * on its first use on a device it looks up that device's copy of the array.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (on different streams or threads) race and give undefined corners; run
+ * them on one stream or one after the other.
+ * Limit: (nx + 1) * (ny + 1) <= 4194304 corners.
+ * Errors: SWE_E_ARG (the limit, and as swe_reconstruct_bathymetry), SWE_E_HIP. */
+int swe_reconstruct_bathymetry_noalloc(int32_t nx, int32_t ny, const float *Hm, const uint8_t *land,
+                                       int32_t iters, float smooth, float *Hc, void *hip_stream);
+
 /* One erosion of the land mask (section "Bathymetry", Figure erode_land):
  * a land cell with a water 4-neighbour (cells outside the domain count as
  * land) becomes water of depth land_depth, its eta the largest eta among

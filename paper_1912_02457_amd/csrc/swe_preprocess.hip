@@ -7,6 +7,7 @@
 #include <cmath>
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "swe_host.h"
@@ -371,6 +372,60 @@ extern "C" int swe_reconstruct_bathymetry(int32_t nx, int32_t ny, const float *H
         cur = nxt;
     }
     return SWE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free reconstruction: the corner plane the rounds ping-pong
+// through lives in a device array of the library's own instead of caller
+// memory.  Each GPU the library runs on holds its own copy of the array
+// until the process ends; in host code the array's name is only a stand-in,
+// so its device address is looked up once per device (hipGetSymbolAddress,
+// with that device current) and only that address is handed to kernels.
+// Every round overwrites every corner of the plane it writes, so nothing in
+// the array has to start at zero.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kStaticScratchFloats = (int64_t)4 << 20;  // 16 MiB: up to 4,194,304 corners
+static __device__ __align__(256) float scratch[kStaticScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's copy of `scratch`
+int static_scratch(float **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return set_error(SWE_E_ARG, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return set_error(SWE_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = static_cast<float *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SWE_OK;
+}
+
+}  // namespace
+
+extern "C" int swe_reconstruct_bathymetry_noalloc(int32_t nx, int32_t ny, const float *Hm, const uint8_t *land,
+                                                  int32_t iters, float smooth, float *Hc, void *hip_stream)
+{
+    if (nx < 1 || ny < 1) return set_error(SWE_E_ARG, "nx and ny must be >= 1");
+    if ((int64_t)(nx + 1) * (int64_t)(ny + 1) > kStaticScratchFloats)
+        return set_error(SWE_E_ARG, "corner plane larger than the static scratch ((nx+1)(ny+1) <= 4194304)");
+    float *scr = nullptr;
+    if (iters > 0) {
+        const int rc = static_scratch(&scr);
+        if (rc != SWE_OK) return rc;
+    }
+    return swe_reconstruct_bathymetry(nx, ny, Hm, land, iters, smooth, Hc, scr, hip_stream);
 }
 
 extern "C" int swe_erode_land(int32_t nx, int32_t ny, const uint8_t *land, const float *Hm, const float *eta,

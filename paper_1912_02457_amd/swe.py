@@ -115,6 +115,8 @@ SIGNATURES = {
     "swe_server_destroy": (None, [_VP]),
     "swe_reconstruct_bathymetry": (C.c_int, [C.c_int32, C.c_int32, _VP, _VP, C.c_int32, C.c_float, _VP, _VP,
                                              _VP]),
+    "swe_reconstruct_bathymetry_noalloc": (C.c_int, [C.c_int32, C.c_int32, _VP, _VP, C.c_int32, C.c_float, _VP,
+                                                     _VP]),
     "swe_erode_land": (C.c_int, [C.c_int32, C.c_int32, _VP, _VP, _VP, _VP, _VP, C.c_float, _VP, _VP, _VP, _VP,
                                  _VP, _VP]),
     "swe_refine2": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _VP, _VP, C.c_float, _VP, _VP, _VP, _VP, _VP]),
@@ -601,6 +603,23 @@ def reconstruct_bathymetry(Hm, land=None, *, iters: int = 10, smooth: float = 0.
                                            _dev(out, torch.float32, (ny + 1, nx + 1), "out"),
                                            _dev(scratch, torch.float32, (ny + 1, nx + 1), "scratch"),
                                            _stream_of(Hm, stream)))
+    return out
+
+
+def reconstruct_bathymetry_noalloc(Hm, land=None, *, iters: int = 10, smooth: float = 0.5, out=None,
+                                   stream=None):
+    """``swe_reconstruct_bathymetry_noalloc``: the same reconstruction with the
+    library's own static scratch (no device allocation in the call; ``out``
+    must then be given by a caller that cannot allocate).  Returns ``out``."""
+    import torch
+    ny, nx = Hm.shape
+    if out is None:
+        out = torch.empty((ny + 1, nx + 1), dtype=torch.float32, device=Hm.device)
+    load_library()
+    _check(_lib.swe_reconstruct_bathymetry_noalloc(nx, ny, _dev(Hm, torch.float32, (ny, nx), "Hm"),
+                                                   _dev(land, torch.uint8, (ny, nx), "land"), int(iters),
+                                                   float(smooth), _dev(out, torch.float32, (ny + 1, nx + 1), "out"),
+                                                   _stream_of(Hm, stream)))
     return out
 
 

@@ -92,6 +92,9 @@ def parse():
                     help="skip the measurement of the float32-state kernels")
     ap.add_argument("--count-tilings", action="store_true",
                     help="profiler run: 3 steps at every tiling the tuner may choose (no tuning, no timing)")
+    ap.add_argument("--profile-workload", default="config2",
+                    help="with --profile-steps / --count-tilings: config2 (default) or convN, the grid-convergence "
+                         "case at N x N")
     ap.add_argument("--float32-state", action="store_true",
                     help="with --profile-steps / --count-tilings: the float32-state kernels instead of the "
                          "compensated ones")
@@ -316,10 +319,12 @@ def bench_single(a, np, torch):
     from paper_1912_02457_amd import Domain
     from workloads import config2
 
-    wl = config2()
-    cells = wl.nx * wl.ny
-    land_cells = int(np.count_nonzero(wl.land)) if wl.land is not None else 0
     if a.count_tilings or a.profile_steps:
+        if a.profile_workload.startswith("conv"):
+            from workloads import convergence_case
+            wl = convergence_case(int(a.profile_workload[4:]))
+        else:
+            wl = config2()
         comp = not a.float32_state
         dom = Domain.from_workload(wl, device="cuda:0", compensated_state=comp)
         if a.count_tilings:
@@ -341,11 +346,14 @@ def bench_single(a, np, torch):
         dom.step(a.profile_steps)
         torch.cuda.synchronize()
         _copy_calibration(a, torch)
-        print(json.dumps({"profiled_steps": a.profile_steps, "compensated": comp,
+        print(json.dumps({"profiled_steps": a.profile_steps, "compensated": comp, "workload": a.profile_workload,
                           "stage_tiling": [dom.stage_tiling(1), dom.stage_tiling(2)]}), flush=True)
         dom.close()
         return None, wl
 
+    wl = config2()
+    cells = wl.nx * wl.ny
+    land_cells = int(np.count_nonzero(wl.land)) if wl.land is not None else 0
     r = time_domain(a, np, torch, wl, True)
     value = cells * a.steps / r["el"]
     (rw1, trw1, tr1, ord1, wv1), (rw2, trw2, tr2, ord2, wv2) = r["tiling"]

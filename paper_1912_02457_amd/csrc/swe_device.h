@@ -78,7 +78,7 @@ struct Dom {
     int nx, ny, pitch, cpitch, P;  // P = 2 ny + 2 nx perimeter cells
     int bc[4];                     // W, E, S, N
     float dx, dy, rdx, rdy, kx, ky; // kx = dx / (2 g)
-    float g, theta, kappa, inv2kappa, half_kappa, courant_q; // courant_q = C / 4
+    float g, theta, kappa, inv2kappa, kappa_sq, courant_q; // courant_q = C / 4
     int friction;
     float fric_c;                  // r, r, or g n^2 (Manning)
     double inv_rho_w;

@@ -64,19 +64,21 @@ struct Lo {
 
 // Value held by lane-1 / lane+1 through a whole-wave DPP shift (wave_shr:1
 // and wave_shl:1 of the GFX9 DPP controls; a VALU operand modifier, no LDS
-// round trip).  Lane 0 / lane 63 receive 0; they are halo lanes whose results
-// are never stored.
+// round trip).  Lane 0 / lane 63 receive 0 (bound_ctrl: the lane without a
+// source reads zero, so no old value has to be set up first); they are halo
+// lanes whose results are never stored.
 constexpr int kDppWaveShl1 = 0x130;
 constexpr int kDppWaveShr1 = 0x138;
-__device__ __forceinline__ int from_left(int v) { return __builtin_amdgcn_update_dpp(0, v, kDppWaveShr1, 0xF, 0xF, false); }
-__device__ __forceinline__ int from_right(int v) { return __builtin_amdgcn_update_dpp(0, v, kDppWaveShl1, 0xF, 0xF, false); }
+__device__ __forceinline__ int from_left(int v) { return __builtin_amdgcn_update_dpp(0, v, kDppWaveShr1, 0xF, 0xF, true); }
+__device__ __forceinline__ int from_right(int v) { return __builtin_amdgcn_update_dpp(0, v, kDppWaveShl1, 0xF, 0xF, true); }
 __device__ __forceinline__ float from_left(float v) { return __int_as_float(from_left(__float_as_int(v))); }
 __device__ __forceinline__ float from_right(float v) { return __int_as_float(from_right(__float_as_int(v))); }
 
-// eq. desing_ours
+// eq. desing_ours; h^2/(2 kappa) + kappa/2 is formed as (h h + kappa^2) /
+// (2 kappa), one uniform operand per instruction
 __device__ __forceinline__ float desing(float h, const Dom &d)
 {
-    float lo = fminf(fmaf(h * h, d.inv2kappa, d.half_kappa), d.kappa);
+    float lo = fminf(fmaf(h, h, d.kappa_sq) * d.inv2kappa, d.kappa);
     float m = fmaxf(fabsf(h), lo);
     // sign(h) with sign(0) = +1: adding +0 turns a -0 into +0
     return copysignf(m, h + 0.f);
@@ -241,14 +243,21 @@ __device__ __forceinline__ F3 cu_flux(float eL, float pL0, float qL0, float eR, 
 }
 
 // face with the land rule: a face touching land carries the reflective-wall
-// flux of its wet side; a face between two land cells carries nothing
+// flux of its wet side; a face between two land cells carries nothing.
+// `anyland` is uniform over the wave (some lane of the rows involved is
+// land); without it the land selects are skipped, which gives bitwise the
+// same flux.
 __device__ __forceinline__ F3 face_flux(float eL, float pL, float qL, float eR, float pR, float qR,
-                                        bool lL, bool lR, float Hf, const Dom &d)
+                                        bool lL, bool lR, bool anyland, float Hf, const Dom &d)
 {
-    float e2R = lR ? eL : eR, p2R = lR ? -pL : pR, q2R = lR ? qL : qR;
-    float e2L = lL ? eR : eL, p2L = lL ? -pR : pL, q2L = lL ? qR : qL;
-    F3 r = cu_flux(e2L, p2L, q2L, e2R, p2R, q2R, Hf, d);
-    if (lL && lR) r.e = r.p = r.q = 0.f;
+    if (anyland) {
+        const float e2R = lR ? eL : eR, p2R = lR ? -pL : pR, q2R = lR ? qL : qR;
+        const float e2L = lL ? eR : eL, p2L = lL ? -pR : pL, q2L = lL ? qR : qL;
+        eL = e2L; pL = p2L; qL = q2L;
+        eR = e2R; pR = p2R; qR = q2R;
+    }
+    F3 r = cu_flux(eL, pL, qL, eR, pR, qR, Hf, d);
+    if (anyland && lL && lR) r.e = r.p = r.q = 0.f;
     return r;
 }
 
@@ -278,6 +287,24 @@ __device__ __forceinline__ float friction_coeff(const Dom &d, float ri, float hu
     return d.fric_c * speed * ra43;
 }
 
+// Face values eta +/- rho of a cell with the wet-dry fix of eq. KxE_adjust:
+// a face value below the bottom (eta_f + H_f < 0) is set to the bottom and
+// the other face takes 2 eta - eta_f, keeping the cell average; first the
+// face on the + side, then the one on the - side.  As max/min: raising
+// the + face to -H_+ is a max, and then the - face (2 eta - that) is the
+// min of itself and 2 eta + H_+ -- exact when the fix applies, and equal
+// to the unfixed value otherwise (up to one rounding when the two are
+// within an ulp).
+__device__ __forceinline__ void positivity_fix(float e, float rho, float Hp, float Hm, float &ep, float &em)
+{
+    ep = e + rho;
+    em = e - rho;
+    ep = fmaxf(ep, -Hp);
+    em = fminf(em, fmaf(2.f, e, Hp));
+    em = fmaxf(em, -Hm);
+    ep = fminf(ep, fmaf(2.f, e, Hm));
+}
+
 // One row of the sliding window (per lane: column i).
 struct Row {
     float e, u, v, f;      // state (ghost-resolved) and Coriolis parameter (NaN: land)
@@ -285,6 +312,7 @@ struct Row {
     float Hw, He, Hs, Hn, Hb;
     float ri;              // 1 / h* of the cell
     int land;
+    bool anyland;          // some lane of the row is land (uniform over the wave)
     float dmL, dmU, dmV;   // y backward differences (this row minus the row below)
     float eN, eS, uN, vN;  // north/south face values once the row was the middle row
 };
@@ -305,6 +333,7 @@ __device__ __forceinline__ void row_terms(Row &R, float cs0, float cs1, float cn
     R.ri = ri;
     float uu = R.u * ri, vv = R.v * ri;
     R.land = isnan(R.f) ? 1 : 0;
+    R.anyland = __ballot(R.land) != 0;
     if (PROJ) {
         float c = __cosf(th), s = __sinf(th);
         float ue = c * uu - s * vv, vn = s * uu + c * vv;
@@ -328,17 +357,18 @@ __device__ __forceinline__ void y_diff(Row &C, const Row &B, const Dom &d)
 // limited y-slopes and N/S face values of row B (eq. hE in its N/S form with
 // the wet-dry fix of eq. KxE_adjust); stores the N values and eS in B and
 // returns the S momenta for the face below B
-__device__ __forceinline__ void y_faces(Row &B, const Row &C, int landA, const Dom &d, float &uS, float &vS)
+__device__ __forceinline__ void y_faces(Row &B, const Row &C, int landA, bool anylandA, const Dom &d, float &uS,
+                                        float &vS)
 {
     const float th = d.theta;
     float sL = limited(B.dmL, C.dmL, th);
     float sU = limited(B.dmU, C.dmU, th);
     float sV = limited(B.dmV, C.dmV, th);
-    if (landA || C.land) sL = sU = sV = 0.f;  // first order next to land
+    // first order next to land (skipped for rows without land nearby)
+    if ((anylandA || C.anyland) && (landA || C.land)) sL = sU = sV = 0.f;
     float rho = 0.5f * sL + d.ky * B.cy;
-    float eN = B.e + rho, eS = B.e - rho;
-    if (eN + B.Hn < 0.f) { eN = -B.Hn; eS = 2.f * B.e - eN; }
-    if (eS + B.Hs < 0.f) { eS = -B.Hs; eN = 2.f * B.e - eS; }
+    float eN, eS;
+    positivity_fix(B.e, rho, B.Hn, B.Hs, eN, eS);
     B.eN = eN;
     B.eS = eS;
     B.uN = B.u + 0.5f * sU;
@@ -351,7 +381,7 @@ __device__ __forceinline__ void y_faces(Row &B, const Row &C, int landA, const D
 // (above, its S values): normal momentum hv, transverse hu
 __device__ __forceinline__ F3 y_flux(const Row &A, const Row &B, float uS, float vS, const Dom &d)
 {
-    return face_flux(A.eN, A.vN, A.uN, B.eS, vS, uS, A.land != 0, B.land != 0, B.Hs, d);
+    return face_flux(A.eN, A.vN, A.uN, B.eS, vS, uS, A.land != 0, B.land != 0, A.anyland || B.anyland, B.Hs, d);
 }
 
 struct TileCtx {
@@ -463,21 +493,24 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
     const float th = d.theta;
     float eL = from_left(A.e), cxL = from_left(A.cx);
     float uL = from_left(A.u), vL = from_left(A.v);
-    int landL = from_left(A.land), landR = from_right(A.land);
     float dmK = A.e - eL - d.kx * (cxL + A.cx);
     float dmU = A.u - uL, dmV = A.v - vL;
     float sK = limited(dmK, from_right(dmK), th);
     float sUx = limited(dmU, from_right(dmU), th);
     float sVx = limited(dmV, from_right(dmV), th);
-    if (landL || landR) sK = sUx = sVx = 0.f;
+    int landR = 0;
+    if (A.anyland) {  // first order next to land (rows with land only)
+        const int landL = from_left(A.land);
+        landR = from_right(A.land);
+        if (landL || landR) sK = sUx = sVx = 0.f;
+    }
     float rx = 0.5f * sK + d.kx * A.cx;
-    float eE = A.e + rx, eW = A.e - rx;
-    if (eE + A.He < 0.f) { eE = -A.He; eW = 2.f * A.e - eE; }
-    if (eW + A.Hw < 0.f) { eW = -A.Hw; eE = 2.f * A.e - eW; }
+    float eE, eW;
+    positivity_fix(A.e, rx, A.He, A.Hw, eE, eW);
     float uE = A.u + 0.5f * sUx, uW = A.u - 0.5f * sUx;
     float vE = A.v + 0.5f * sVx, vW = A.v - 0.5f * sVx;
     F3 Fe = face_flux(eE, uE, vE, from_right(eW), from_right(uW), from_right(vW), A.land != 0, landR != 0,
-                      A.He, d);
+                      A.anyland, A.He, d);
     float Fwe = from_left(Fe.e), Fwp = from_left(Fe.p), Fwq = from_left(Fe.q);
     // every lane computes; only output lanes over water store (no early exit,
     // so the x and y work of neighbouring rows can be interleaved)
@@ -741,10 +774,10 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
     y_diff(R1, R0, d);
     load(R2, y0);
     y_diff(R2, R1, d);
-    y_faces(R1, R2, R0.land, d, uS, vS);
+    y_faces(R1, R2, R0.land, R0.anyland, d, uS, vS);
     load(R0, y0 + 1);
     y_diff(R0, R2, d);
-    y_faces(R2, R0, R1.land, d, uS, vS);
+    y_faces(R2, R0, R1.land, R1.anyland, d, uS, vS);
     F3 Gs = y_flux(R1, R2, uS, vS, d);
 
     // steady state: A = row k-2 (output), B = row k-1, C = row k
@@ -767,7 +800,7 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
         load(C, k);
         y_diff(C, B, d);
         float us, vs;
-        y_faces(B, C, A.land, d, us, vs);
+        y_faces(B, C, A.land, A.anyland, d, us, vs);
         F3 Gn = y_flux(A, B, us, vs, d);
         // a row whose output cells are all land has nothing to update
         if (__ballot(c.out_lane && !A.land) != 0)

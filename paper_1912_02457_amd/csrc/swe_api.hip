@@ -393,6 +393,7 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
     D.rdx = (float)(1.0 / p->dx); D.rdy = (float)(1.0 / p->dy);
     D.kx = (float)(p->dx / (2.0 * p->g)); D.ky = (float)(p->dy / (2.0 * p->g));
     D.g = (float)p->g; D.theta = (float)p->theta; D.kappa = (float)p->kappa;
+    D.theta2 = (float)(2.0 * p->theta);
     D.inv2kappa = (float)(1.0 / (2.0 * p->kappa)); D.kappa_sq = (float)(p->kappa * p->kappa);
     D.courant_q = (float)(0.25 * p->courant);
     D.friction = p->friction;

@@ -79,6 +79,7 @@ struct Dom {
     int bc[4];                     // W, E, S, N
     float dx, dy, rdx, rdy, kx, ky; // kx = dx / (2 g)
     float g, theta, kappa, inv2kappa, kappa_sq, courant_q; // courant_q = C / 4
+    float theta2;                  // 2 theta (the limiter works on twice the slopes)
     int friction;
     float fric_c;                  // r, r, or g n^2 (Manning)
     double inv_rho_w;

@@ -84,13 +84,16 @@ __device__ __forceinline__ float desing(float h, const Dom &d)
     return copysignf(m, h + 0.f);
 }
 
-// generalized minmod of theta*backward, central, theta*forward differences
-__device__ __forceinline__ float limited(float dm, float dp, float th)
+// TWICE the generalized minmod of theta*backward, central, theta*forward
+// differences: minmod(2 theta dm, dm + dp, 2 theta dp) with th2 = 2 theta
+// (scaling by two is exact, so callers take a quarter of it where the
+// slope's half is used, bitwise the same as halving the minmod).  minmod of
+// three numbers is the median of (their minimum, 0, their maximum): the
+// minimum if all are positive, the maximum if all are negative, else 0.
+__device__ __forceinline__ float limited2(float dm, float dp, float th2)
 {
-    float a = th * dm, b = 0.5f * (dm + dp), c = th * dp;
-    float mn = fminf(a, fminf(b, c)), mx = fmaxf(a, fmaxf(b, c));
-    // mn if all three are positive, mx if all are negative, else 0
-    return fmaxf(mn, 0.f) + fminf(mx, 0.f);
+    const float a = th2 * dm, b = dm + dp, c = th2 * dp;
+    return __builtin_amdgcn_fmed3f(fminf(a, fminf(b, c)), 0.f, fmaxf(a, fmaxf(b, c)));
 }
 
 __device__ __forceinline__ void time_weights(int n, const double *ts, double tau, int &k, double &s)
@@ -360,21 +363,22 @@ __device__ __forceinline__ void y_diff(Row &C, const Row &B, const Dom &d)
 __device__ __forceinline__ void y_faces(Row &B, const Row &C, int landA, bool anylandA, const Dom &d, float &uS,
                                         float &vS)
 {
-    const float th = d.theta;
-    float sL = limited(B.dmL, C.dmL, th);
-    float sU = limited(B.dmU, C.dmU, th);
-    float sV = limited(B.dmV, C.dmV, th);
+    // twice the limited slopes (limited2)
+    const float th2 = d.theta2;
+    float sL = limited2(B.dmL, C.dmL, th2);
+    float sU = limited2(B.dmU, C.dmU, th2);
+    float sV = limited2(B.dmV, C.dmV, th2);
     // first order next to land (skipped for rows without land nearby)
     if ((anylandA || C.anyland) && (landA || C.land)) sL = sU = sV = 0.f;
-    float rho = 0.5f * sL + d.ky * B.cy;
+    float rho = 0.25f * sL + d.ky * B.cy;
     float eN, eS;
     positivity_fix(B.e, rho, B.Hn, B.Hs, eN, eS);
     B.eN = eN;
     B.eS = eS;
-    B.uN = B.u + 0.5f * sU;
-    B.vN = B.v + 0.5f * sV;
-    uS = B.u - 0.5f * sU;
-    vS = B.v - 0.5f * sV;
+    B.uN = B.u + 0.25f * sU;
+    B.vN = B.v + 0.25f * sV;
+    uS = B.u - 0.25f * sU;
+    vS = B.v - 0.25f * sV;
 }
 
 // flux through the face between row A (below, its N values) and row B
@@ -490,25 +494,26 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
                                            float e0, float u0, float v0, bool lo_ok, const FrsPre &fp,
                                            const Dom &d, float &wmax_loc, int &bad)
 {
-    const float th = d.theta;
+    const float th2 = d.theta2;
     float eL = from_left(A.e), cxL = from_left(A.cx);
     float uL = from_left(A.u), vL = from_left(A.v);
     float dmK = A.e - eL - d.kx * (cxL + A.cx);
     float dmU = A.u - uL, dmV = A.v - vL;
-    float sK = limited(dmK, from_right(dmK), th);
-    float sUx = limited(dmU, from_right(dmU), th);
-    float sVx = limited(dmV, from_right(dmV), th);
+    // twice the limited slopes (limited2)
+    float sK = limited2(dmK, from_right(dmK), th2);
+    float sUx = limited2(dmU, from_right(dmU), th2);
+    float sVx = limited2(dmV, from_right(dmV), th2);
     int landR = 0;
     if (A.anyland) {  // first order next to land (rows with land only)
         const int landL = from_left(A.land);
         landR = from_right(A.land);
         if (landL || landR) sK = sUx = sVx = 0.f;
     }
-    float rx = 0.5f * sK + d.kx * A.cx;
+    float rx = 0.25f * sK + d.kx * A.cx;
     float eE, eW;
     positivity_fix(A.e, rx, A.He, A.Hw, eE, eW);
-    float uE = A.u + 0.5f * sUx, uW = A.u - 0.5f * sUx;
-    float vE = A.v + 0.5f * sVx, vW = A.v - 0.5f * sVx;
+    float uE = A.u + 0.25f * sUx, uW = A.u - 0.25f * sUx;
+    float vE = A.v + 0.25f * sVx, vW = A.v - 0.25f * sVx;
     F3 Fe = face_flux(eE, uE, vE, from_right(eW), from_right(uW), from_right(vW), A.land != 0, landR != 0,
                       A.anyland, A.He, d);
     float Fwe = from_left(Fe.e), Fwp = from_left(Fe.p), Fwq = from_left(Fe.q);

@@ -26,6 +26,7 @@
 #include <hip/hip_ext.h>
 
 #include "swe_device.h"
+#include "swe_maps.h"
 
 namespace swe {
 
@@ -136,71 +137,6 @@ __device__ __forceinline__ void wind_at(const Dom &d, double tau, float &wx, flo
     wy = (float)(ay * d.inv_rho_w);
 }
 
-// Ghost cells.  Wall ghosts mirror the state with the normal momentum and f
-// negated (eq. tradWallBCx and f(-x) = -f(x) of eq. KxWallBCReq); periodic
-// ghosts wrap; nested ghosts take the external state at the stage time and
-// the f / north angle stored for them at init.  The mapping is split into a
-// column part, fixed for a lane over a whole tile, and a row part, the same
-// for every lane of a row.
-struct ColMap {
-    int ci;       // source column
-    int cc0, cc1; // source corner columns of the cell's west and east corners
-    float su, sf; // sign of hu and f (wall ghost)
-    int nside;    // nested side 0 (W) / 1 (E) for a nested ghost column, else -1
-    int nlayer;   // 0 for the ghost next to the domain, 1 for the outer one
-};
-
-struct RowMap {
-    int cr;       // source row
-    int crc;      // source corner row of the cell's north corners
-    float sv, sf; // sign of hv and f (wall ghost)
-    int nside;    // nested side 2 (S) / 3 (N) for a nested ghost row, else -1
-    int nlayer;
-};
-
-__device__ __forceinline__ int map_corner(int c, int n, int lo, int hi);
-
-// i in [-2, nx+1]
-__device__ __forceinline__ ColMap col_map(const Dom &d, int i)
-{
-    const int nx = d.nx;
-    ColMap m;
-    m.ci = i; m.su = 1.f; m.sf = 1.f; m.nside = -1; m.nlayer = 0;
-    if (i < 0) {
-        if (d.bc[0] == BC_PERIODIC) m.ci = i + nx;
-        else { m.ci = -1 - i; if (d.bc[0] == BC_WALL) { m.su = -1.f; m.sf = -1.f; } else { m.nside = 0; m.nlayer = -1 - i; } }
-    } else if (i >= nx) {
-        if (d.bc[1] == BC_PERIODIC) m.ci = i - nx;
-        else { m.ci = 2 * nx - 1 - i; if (d.bc[1] == BC_WALL) { m.su = -1.f; m.sf = -1.f; } else { m.nside = 1; m.nlayer = i - nx; } }
-    }
-    m.cc0 = map_corner(i, nx, d.bc[0], d.bc[1]);
-    m.cc1 = map_corner(i + 1, nx, d.bc[0], d.bc[1]);
-    return m;
-}
-
-// r in [-2, ny+1]
-__device__ __forceinline__ RowMap row_map(const Dom &d, int r)
-{
-    const int ny = d.ny;
-    RowMap m;
-    m.cr = r; m.sv = 1.f; m.sf = 1.f; m.nside = -1; m.nlayer = 0;
-    if (r < 0) {
-        if (d.bc[2] == BC_PERIODIC) m.cr = r + ny;
-        else { m.cr = -1 - r; if (d.bc[2] == BC_WALL) { m.sv = -1.f; m.sf = -1.f; } else { m.nside = 2; m.nlayer = -1 - r; } }
-    } else if (r >= ny) {
-        if (d.bc[3] == BC_PERIODIC) m.cr = r - ny;
-        else { m.cr = 2 * ny - 1 - r; if (d.bc[3] == BC_WALL) { m.sv = -1.f; m.sf = -1.f; } else { m.nside = 3; m.nlayer = r - ny; } }
-    }
-    m.crc = map_corner(r + 1, ny, d.bc[2], d.bc[3]);
-    return m;
-}
-
-__device__ __forceinline__ int map_corner(int c, int n, int lo, int hi)
-{
-    if (c < 0) return lo == BC_PERIODIC ? c + n : -c;
-    if (c > n) return hi == BC_PERIODIC ? c - n : 2 * n - c;
-    return c;
-}
 
 
 struct F3 { float e, p, q; };
@@ -448,23 +384,11 @@ struct FrsPre {
     float a[3], b[3];
 };
 
-// nearest nested side of cell (i, o) (ties W, E, S, N) and its distance in
-// cells; best = -1 without nested sides
-__device__ __forceinline__ void frs_side(const Dom &d, int i, int o, int &best, int &dd)
-{
-    const int nx = d.nx, ny = d.ny;
-    int dist[4] = {i, nx - 1 - i, o, ny - 1 - o};
-    best = -1;
-    dd = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if (d.bc[k] == BC_NESTED && (best < 0 || dist[k] < dd)) { best = k; dd = dist[k]; }
-}
-
 __device__ __forceinline__ FrsPre frs_prefetch(const Dom &d, const TileCtx &c)
 {
     FrsPre f;
     const int nx = d.nx, ny = d.ny, i = c.i, o = c.o;
+    // boundary-table entries on the four sides (frs_candidates in swe_maps.h)
     int idxs[4] = {o, ny + o, 2 * ny + i, 2 * ny + nx + i};
     int best, dd;
     frs_side(d, i, o, best, dd);
@@ -686,14 +610,16 @@ __device__ __forceinline__ RawRow load_row(const Dom &d, const float *__restrict
     } else {
         // A lane in a ghost column only ever contributes rows inside [0, ny);
         // its rows outside (diagonal ghosts) load some in-bounds value that is
-        // never used.
+        // never used.  (ghost_src in swe_maps.h computes the same sources for
+        // the host-side bounds check; kept inline here, where the register
+        // allocation of the kernels that hold it is tight.)
         const RowMap rm = row_map(d, r);  // the same for all lanes
         const bool yin = r >= 0 && r < d.ny;
         int side = -1, idx = 0, layer = 0;
         if (yin && cm.nside >= 0) {
             side = cm.nside; layer = cm.nlayer; idx = cm.nside == 0 ? r : d.ny + r;
         } else if (!yin && rm.nside >= 0) {
-            const int ii = min(max(il, 0), d.nx - 1);
+            const int ii = imin(imax(il, 0), d.nx - 1);
             side = rm.nside; layer = rm.nlayer; idx = rm.nside == 2 ? 2 * d.ny + ii : 2 * d.ny + d.nx + ii;
         }
         if (side >= 0) {

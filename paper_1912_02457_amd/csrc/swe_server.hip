@@ -12,6 +12,7 @@
 #include <memory>
 #include <mutex>
 
+#include "swe_arena.h"
 #include "swe_host.h"
 
 using namespace swe;
@@ -42,58 +43,6 @@ static_assert(offsetof(CtrlHead, t) == offsetof(Ctrl, t), "control block layout"
 static_assert(offsetof(CtrlHead, flags) == offsetof(Ctrl, flags), "control block layout");
 static_assert(offsetof(CtrlHead, steps) == offsetof(Ctrl, steps), "control block layout");
 static_assert(sizeof(CtrlHead) <= sizeof(Ctrl), "control block layout");
-
-// First-fit allocator over [0, size) with coalescing of free neighbours.
-class Arena {
-public:
-    void reset(size_t size)
-    {
-        size_ = size;
-        free_.clear();
-        if (size) free_[0] = size;
-        used_ = peak_ = 0;
-    }
-    bool alloc(size_t bytes, size_t *off)
-    {
-        bytes = align_up(std::max<size_t>(bytes, 1), kAlign);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes) continue;
-            *off = it->first;
-            size_t rest = it->second - bytes, at = it->first + bytes;
-            free_.erase(it);
-            if (rest) free_[at] = rest;
-            used_ += bytes;
-            peak_ = std::max(peak_, used_);
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes)
-    {
-        bytes = align_up(std::max<size_t>(bytes, 1), kAlign);
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t size() const { return size_; }
-    size_t used() const { return used_; }
-    size_t peak() const { return peak_; }
-
-private:
-    size_t size_ = 0, used_ = 0, peak_ = 0;
-    std::map<size_t, size_t> free_;
-};
 
 struct Pending {
     swe_request r{};  // pointers below re-aimed at the owned copies

@@ -229,8 +229,10 @@ int swe_status(swe_domain *d);
 
 /* Measures both stage kernels of this domain for rows per tile in {2..64}
  * and, around the fastest, for tails of 1-4-row bands (swe_set_stage_tiling),
- * then the winner under the other tile orders (a few launches each), and
- * keeps the fastest tiling per stage.  The state and the
+ * then the winner under the other tile orders (a few launches each), times
+ * the three fastest candidates again, and keeps the fastest tiling per
+ * stage.  Before anything is timed, stage-1 launches run for about 25 ms of
+ * device time so that the clocks have come up.  The state and the
  * control block are saved to host memory first and restored afterwards, so
  * the simulation does not advance.  *rows_per_wave gets stage 1's choice
  * (may be NULL; swe_get_tiling reports each stage).  Synchronises.  Errors:

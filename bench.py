@@ -40,11 +40,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 #   float32 state (the paper's):
 #     stage 1: read eta,hu,hv (12) + Hc (4) + f (4), write Q* (12)            = 32
 #     stage 2: read Q* (12) + Q^n (12) + Hc (4) + f (4), write Q^n+1 (12)     = 44
-#   compensated state (each stored value with its float32 rounding error,
-#   i.e. 24 B of state per cell):
-#     stage 1: the above + read 3 error planes of Q^n, write 3 of Q*          = 56
-#     stage 2: the above + read 3 error planes of Q* and 3 of Q^n, write 3    = 80
-BYTES = {False: {1: 32, 2: 44}, True: {1: 56, 2: 80}}
+#   compensated state (each stored value with its rounding error in 16 bits,
+#   i.e. 18 B of state per cell):
+#     stage 1: the above + read 3 error planes of Q^n (6), write 3 of Q* (6)  = 44
+#     stage 2: the above + read 3 of Q* and 3 of Q^n (12), write 3 (6)        = 62
+BYTES = {False: {1: 32, 2: 44}, True: {1: 44, 2: 62}}
 # Secondary: the VALU issue rate.  Without packed FP32 (excluded by the build
 # flags) the issue rate is 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12
 # lane-instructions/s.
@@ -69,9 +69,10 @@ def parse():
     ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000)
-    ap.add_argument("--serve-max-active", type=int, default=64)
+    ap.add_argument("--serve-max-active", type=int, default=128)
     ap.add_argument("--serve-steps-per-tick", type=int, default=24)
     ap.add_argument("--serve-rows", type=int, default=0, help="rows per tile of the server's ensemble (0 = default)")
+    ap.add_argument("--serve-chunk", type=int, default=0, help="tiles per queue pop of the server's ensemble (0 = default)")
     ap.add_argument("--serve-unloaded-requests", type=int, default=150,
                     help="requests of the unloaded stream (0 = skip it)")
     ap.add_argument("--serve-unloaded-spread", type=float, default=8.0,
@@ -83,6 +84,8 @@ def parse():
     ap.add_argument("--serve-full", action="store_true",
                     help="serve the request stream as specified (2000 requests, 20/s, horizons 1-24 h) and a "
                          "second stream at --serve-rate-low requests/s")
+    ap.add_argument("--serve-rate", type=float, default=20.0,
+                    help="with --serve-full: arrival rate of the specified stream (requests/s)")
     ap.add_argument("--serve-rate-low", type=float, default=5.0)
     ap.add_argument("--serve-only", action="store_true", help="only the serving section (JSON with it alone)")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -667,12 +670,13 @@ def bench_serving(a, torch):
 
     out = {}
     if a.serve_full:
-        reqs = config5_requests()
+        reqs = config5_requests(rate=a.serve_rate)
         arrivals = np.array([r["arrival"] for r in reqs])
         horizons = [r["horizon"] for r in reqs]
         out = _serve_stream(a, torch, reqs, arrivals, horizons, scale=1.0)
-        out["stream"] = "as specified: 2000 requests, Poisson 20/s, horizons U[1, 24] h"
-        out["one_by_one"] = serve_one_by_one(reqs[:a.serve_baseline_requests], horizons, torch)
+        out["stream"] = f"as specified: 2000 requests, Poisson {a.serve_rate:g}/s, horizons U[1, 24] h"
+        if a.serve_baseline_requests > 0:
+            out["one_by_one"] = serve_one_by_one(reqs[:a.serve_baseline_requests], horizons, torch)
         if a.serve_rate_low > 0:
             low = config5_requests(rate=a.serve_rate_low)
             arr_low = np.array([r["arrival"] for r in low])
@@ -687,7 +691,8 @@ def bench_serving(a, torch):
         out = _serve_stream(a, torch, reqs, arrivals, horizons, scale=sc)
         out["stream"] = (f"stand-in for the specified stream: {len(reqs)} requests, horizons and inter-arrival "
                          f"times x {sc} (same offered load), so that it fits the benchmark's run time")
-        out["one_by_one"] = serve_one_by_one(reqs[:a.serve_baseline_requests], horizons, torch)
+        if a.serve_baseline_requests > 0:
+            out["one_by_one"] = serve_one_by_one(reqs[:a.serve_baseline_requests], horizons, torch)
         if a.serve_unloaded_requests > 0:
             n = a.serve_unloaded_requests
             u = _serve_stream(a, torch, reqs[:n], arrivals[:n] * a.serve_unloaded_spread, horizons[:n], scale=sc)
@@ -740,7 +745,7 @@ def _serve_stream(a, torch, reqs, arrivals, horizons, scale):
 
     sc = scale
     srv = Server(48 << 30, max_active=a.serve_max_active, steps_per_tick=a.serve_steps_per_tick,
-                 rows_per_wave=a.serve_rows, device="cuda:0")
+                 rows_per_wave=a.serve_rows, chunk=a.serve_chunk, device="cuda:0")
     done_at = {}
     submitted = threading.Event()
     errors = []
@@ -822,7 +827,7 @@ def _serve_stream(a, torch, reqs, arrivals, horizons, scale):
         "saturated_s": sat_s,
         "span_s": span, "busy_s": busy_s, "mean_active": active_time / max(busy_s, 1e-9),
         "ticks": st["ticks"], "steps_per_tick": a.serve_steps_per_tick, "max_active": a.serve_max_active,
-        "rows_per_wave": a.serve_rows,
+        "rows_per_wave": a.serve_rows, "chunk": a.serve_chunk,
         "arena_peak_GiB": st["arena_peak"] / 2**30,
         "host_s": {k[5:-2]: round(st[k], 3) for k in st if k.startswith("host_")},
     }

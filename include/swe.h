@@ -77,10 +77,12 @@ typedef struct swe_params {
                                 (reads the north angle every stage) */
     int32_t compensated_state;/* 0: the state is stored in float32, as in the paper;
                                 1: each stored value of Q^n and Q* also keeps its
-                                rounding error (a second float32 plane per field),
-                                updated by an error-free sum, so that storing the
-                                state rounds away nothing across steps; the
-                                arithmetic of a stage stays float32.  Six more
+                                rounding error (a second plane per field holding
+                                the error's upper 16 bits, a bfloat16), updated
+                                by an error-free sum, so that storing the state
+                                rounds away about 2^-10 of a float32 ulp per
+                                step instead of up to half of one; the arithmetic
+                                of a stage stays float32.  Six more half-size
                                 planes of workspace. */
 } swe_params;
 
@@ -309,7 +311,7 @@ int swe_ensemble_workspace_bytes(swe_domain *const *members, int32_t n, int32_t 
 /* Group n >= 1 ready domains (boundary data set where nested; all with the
  * same north_projection) into an ensemble using the caller's device workspace
  * (256-byte aligned, borrowed until swe_ensemble_destroy) and stream.
- * chunk = work items taken per atomic (0 = default 4).  Synchronises. */
+ * chunk = work items taken per atomic (0 = default 1).  Synchronises. */
 int swe_ensemble_create(swe_domain *const *members, int32_t n, void *dev_workspace, size_t bytes,
                         void *hip_stream, int32_t rows_per_wave, int32_t chunk, swe_ensemble **out);
 

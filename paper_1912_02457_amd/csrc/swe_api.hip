@@ -50,7 +50,7 @@ Layout make_layout(const swe_params &p, int max_wind, int max_bnd)
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, kAlign); return o; };
     L.eta = take(plane); L.hu = take(plane); L.hv = take(plane);
     L.eta1 = take(plane); L.hu1 = take(plane); L.hv1 = take(plane);
-    const size_t lo = p.compensated_state ? plane : 0;
+    const size_t lo = p.compensated_state ? plane / 2 : 0;  // 16-bit rounding errors
     L.eta_lo = take(lo); L.hu_lo = take(lo); L.hv_lo = take(lo);
     L.eta1_lo = take(lo); L.hu1_lo = take(lo); L.hv1_lo = take(lo);
     L.Hc = take(cplane);
@@ -231,9 +231,9 @@ int copy_state_to_star(swe_domain *d)
     HIP_TRY(hipMemcpyAsync(d->dom.hu1, d->dom.hu, plane, hipMemcpyDeviceToDevice, d->stream));
     HIP_TRY(hipMemcpyAsync(d->dom.hv1, d->dom.hv, plane, hipMemcpyDeviceToDevice, d->stream));
     // a state handed in as float32 values carries no rounding error yet
-    float *lo[6] = {d->dom.eta_lo, d->dom.hu_lo, d->dom.hv_lo, d->dom.eta1_lo, d->dom.hu1_lo, d->dom.hv1_lo};
-    for (float *q : lo)
-        if (q) HIP_TRY(hipMemsetAsync(q, 0, plane, d->stream));
+    uint16_t *lo[6] = {d->dom.eta_lo, d->dom.hu_lo, d->dom.hv_lo, d->dom.eta1_lo, d->dom.hu1_lo, d->dom.hv1_lo};
+    for (uint16_t *q : lo)
+        if (q) HIP_TRY(hipMemsetAsync(q, 0, plane / 2, d->stream));
     return SWE_OK;
 }
 
@@ -406,8 +406,9 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
     D.eta = (float *)(w + L.eta); D.hu = (float *)(w + L.hu); D.hv = (float *)(w + L.hv);
     D.eta1 = (float *)(w + L.eta1); D.hu1 = (float *)(w + L.hu1); D.hv1 = (float *)(w + L.hv1);
     if (p->compensated_state) {
-        D.eta_lo = (float *)(w + L.eta_lo); D.hu_lo = (float *)(w + L.hu_lo); D.hv_lo = (float *)(w + L.hv_lo);
-        D.eta1_lo = (float *)(w + L.eta1_lo); D.hu1_lo = (float *)(w + L.hu1_lo); D.hv1_lo = (float *)(w + L.hv1_lo);
+        D.eta_lo = (uint16_t *)(w + L.eta_lo); D.hu_lo = (uint16_t *)(w + L.hu_lo); D.hv_lo = (uint16_t *)(w + L.hv_lo);
+        D.eta1_lo = (uint16_t *)(w + L.eta1_lo); D.hu1_lo = (uint16_t *)(w + L.hu1_lo);
+        D.hv1_lo = (uint16_t *)(w + L.hv1_lo);
     }
     D.Hc = (const float *)(w + L.Hc);
     D.f = (const float *)(w + L.f);
@@ -1008,12 +1009,15 @@ int swe_autotune_tiling(swe_domain *d, int32_t *rows_per_wave)
     Ctrl saved;
     if ((rc = read_ctrl(d, &saved))) return rc;
     const int nx = d->p.nx, ny = d->p.ny;
-    const size_t plane = (size_t)nx * ny, row = (size_t)nx * sizeof(float), dp = (size_t)d->dom.pitch * sizeof(float);
+    const size_t plane = (size_t)nx * ny;
     if ((rc = ensure_pinned_state(d))) return rc;
-    float *q[6] = {d->dom.eta, d->dom.hu, d->dom.hv, d->dom.eta_lo, d->dom.hu_lo, d->dom.hv_lo};
+    // the three value planes (float32) and the three rounding-error planes (16 bits)
+    void *q[6] = {d->dom.eta, d->dom.hu, d->dom.hv, d->dom.eta_lo, d->dom.hu_lo, d->dom.hv_lo};
     const int nq = d->p.compensated_state ? 6 : 3;
+    auto esz = [](int k) { return k < 3 ? sizeof(float) : sizeof(uint16_t); };
     for (int k = 0; k < nq; ++k)
-        HIP_TRY(hipMemcpy2DAsync(d->pinned_state + k * plane, row, q[k], dp, row, ny, hipMemcpyDeviceToHost, d->stream));
+        HIP_TRY(hipMemcpy2DAsync(d->pinned_state + k * plane, nx * esz(k), q[k], d->dom.pitch * esz(k), nx * esz(k),
+                                 ny, hipMemcpyDeviceToHost, d->stream));
     Tiling T1 = d->T[0], T2 = d->T[1];
     hipError_t se = settle_clocks(d);
     rc = se != hipSuccess ? hip_fail(se, "settle_clocks") : sweep_stage(d, 1, &T1);
@@ -1024,7 +1028,8 @@ int swe_autotune_tiling(swe_domain *d, int32_t *rows_per_wave)
     }
     // the state and control block go back even when the sweep failed
     for (int k = 0; k < nq; ++k)
-        HIP_TRY(hipMemcpy2DAsync(q[k], dp, d->pinned_state + k * plane, row, row, ny, hipMemcpyHostToDevice, d->stream));
+        HIP_TRY(hipMemcpy2DAsync(q[k], d->dom.pitch * esz(k), d->pinned_state + k * plane, nx * esz(k), nx * esz(k),
+                                 ny, hipMemcpyHostToDevice, d->stream));
     HIP_TRY(hipMemcpyAsync(d->dom.ctrl, &saved, sizeof(Ctrl), hipMemcpyHostToDevice, d->stream));
     HIP_TRY(hipStreamSynchronize(d->stream));
     if (rc) return rc;

@@ -89,9 +89,10 @@ struct Dom {
     float *eta, *hu, *hv;          // Q^n, updated in place by stage 2
     float *eta1, *hu1, *hv1;       // Q*
     // compensated state (swe_params.compensated_state): the rounding error of
-    // each stored value of Q^n and Q*, so that value + error carries the
-    // state to about twice the float32 precision; NULL when off
-    float *eta_lo, *hu_lo, *hv_lo, *eta1_lo, *hu1_lo, *hv1_lo;
+    // each stored value of Q^n and Q*, kept as the upper 16 bits of its
+    // float32 value (bfloat16, [ny][pitch]), so that value + error carries
+    // the state to about 2^-10 of a float32 ulp; NULL when off
+    uint16_t *eta_lo, *hu_lo, *hv_lo, *eta1_lo, *hu1_lo, *hv1_lo;
     const float *Hc, *f, *north;
     const float *fghost, *nghost;  // [2 layers][P] f and north angle of nested ghost cells
     const float *frs_alpha;        // [kMaxFrs] 1 - tanh(d / d0)

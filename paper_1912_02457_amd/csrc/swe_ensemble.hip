@@ -22,7 +22,11 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 constexpr int kEnsGraphChunk = 16;
 constexpr int kDefaultRows = 16;
-constexpr int kDefaultChunk = 4;
+// One item per atomic: the items of a member differ little in cost, and
+// taking several at once leaves the last waves of a launch with uneven
+// loads (measured on 128 served-size domains: 2.8e10 cell-updates/s with 1,
+// 2.0e10 with 4).
+constexpr int kDefaultChunk = 1;
 
 struct EnsLayout {
     size_t mem, items, ctrl, total;

@@ -50,6 +50,22 @@ __device__ __forceinline__ void st(float *__restrict__ base, uint32_t off, float
 }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// Rounding errors of the compensated state are stored in 16 bits: the upper
+// half of the float32 error, rounded to nearest (ties away from zero), i.e. a
+// bfloat16.  An error is at most half an ulp of its value, so the pair keeps
+// the value to about 2^-10 of a float32 ulp.  A load takes two more bits of
+// address arithmetic and one shift; a store one add.
+__device__ __forceinline__ float ld_lo(const uint16_t *__restrict__ base, uint32_t off)
+{
+    const uint32_t b = *reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(base) + (off << 1));
+    return __uint_as_float(b << 16);
+}
+__device__ __forceinline__ void st_lo(uint16_t *__restrict__ base, uint32_t off, float v)
+{
+    *reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(base) + (off << 1)) =
+        (uint16_t)((__float_as_uint(v) + 0x8000u) >> 16);
+}
+
 // a + b = s + err exactly (Knuth's TwoSum, no assumption on the magnitudes)
 __device__ __forceinline__ float two_sum(float a, float b, float &err)
 {
@@ -475,13 +491,13 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
     // are used (held across the row they would raise the register count)
     Lo lo{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (COMP && lo_ok) {
-        lo.e0 = ld(d.eta_lo, oo);
-        lo.u0 = ld(d.hu_lo, oo);
-        lo.v0 = ld(d.hv_lo, oo);
+        lo.e0 = ld_lo(d.eta_lo, oo);
+        lo.u0 = ld_lo(d.hu_lo, oo);
+        lo.v0 = ld_lo(d.hv_lo, oo);
         if (STAGE == 2) {
-            lo.e1 = ld(d.eta1_lo, oo);
-            lo.u1 = ld(d.hu1_lo, oo);
-            lo.v1 = ld(d.hv1_lo, oo);
+            lo.e1 = ld_lo(d.eta1_lo, oo);
+            lo.u1 = ld_lo(d.hu1_lo, oo);
+            lo.v1 = ld_lo(d.hv1_lo, oo);
         }
     }
     if (STAGE == 1) {
@@ -497,9 +513,9 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
                 st(d.eta1, oo, en);
                 st(d.hu1, oo, un);
                 st(d.hv1, oo, vn);
-                st(d.eta1_lo, oo, le);
-                st(d.hu1_lo, oo, lu);
-                st(d.hv1_lo, oo, lv);
+                st_lo(d.eta1_lo, oo, le);
+                st_lo(d.hu1_lo, oo, lu);
+                st_lo(d.hv1_lo, oo, lv);
             }
         } else {
             float en = A.e + dt * Me;
@@ -553,9 +569,9 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
             st(d.hu, oo, un);
             st(d.hv, oo, vn);
             if (COMP) {
-                st(d.eta_lo, oo, le);
-                st(d.hu_lo, oo, lu);
-                st(d.hv_lo, oo, lv);
+                st_lo(d.eta_lo, oo, le);
+                st_lo(d.hu_lo, oo, lu);
+                st_lo(d.hv_lo, oo, lv);
             }
         }
         // eq. cfl on the new state

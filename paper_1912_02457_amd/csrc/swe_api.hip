@@ -43,8 +43,11 @@ int pitch_of(int n) { return (int)align_up((size_t)n, 64); }
 Layout make_layout(const swe_params &p, int max_wind, int max_bnd)
 {
     Layout L;
-    size_t plane = (size_t)p.ny * pitch_of(p.nx) * sizeof(float);
-    size_t cplane = (size_t)(p.ny + 1) * pitch_of(p.nx + 1) * sizeof(float);
+    // framed planes (swe_device.h): cells -2 .. nx+1 (and the last strip's
+    // reach) by -2 .. ny+1, corners one row and column more
+    const int fc = frame_cols(p.nx);
+    size_t plane = (size_t)frame_rows(p.ny) * pitch_of(fc) * sizeof(float);
+    size_t cplane = (size_t)(frame_rows(p.ny) + 1) * pitch_of(fc + 1) * sizeof(float);
     size_t P = 2 * (size_t)p.ny + 2 * (size_t)p.nx;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, kAlign); return o; };
@@ -73,10 +76,12 @@ int validate(const swe_params *p)
 {
     if (!p) return fail(SWE_E_ARG, "params is NULL");
     if (p->nx < 2 || p->ny < 2) return fail(SWE_E_ARG, "nx and ny must be >= 2");
-    // the kernels address a plane with 32-bit byte offsets: the corner-depth
-    // plane, the largest, must stay below 4 GiB (about 1.07e9 cells)
+    // the kernels address a plane with 32-bit byte offsets: the framed
+    // corner-depth plane, the largest, must stay below 4 GiB (about 1.07e9
+    // cells)
     if (p->nx > (1 << 29) || p->ny > (1 << 29) ||
-        (int64_t)(p->ny + 1) * (int64_t)(((int64_t)p->nx + 1 + 63) / 64 * 64) * 4 >= ((int64_t)1 << 32))
+        (int64_t)(frame_rows(p->ny) + 1) * (int64_t)(((int64_t)frame_cols(p->nx) + 1 + 63) / 64 * 64) * 4 >=
+            ((int64_t)1 << 32))
         return fail(SWE_E_ARG, "domain too large: one plane must stay below 4 GiB");
     if (!(std::isfinite(p->dx) && p->dx > 0 && std::isfinite(p->dy) && p->dy > 0))
         return fail(SWE_E_ARG, "dx and dy must be finite and > 0");
@@ -224,9 +229,12 @@ int reset_time_and_cfl(swe_domain *d, double t)
     return SWE_OK;
 }
 
+// A new Q^n (init, set_state): its frame for the time of the current
+// parity, then Q* (frames included) as a copy of it.
 int copy_state_to_star(swe_domain *d)
 {
-    size_t plane = (size_t)d->p.ny * d->dom.pitch * sizeof(float);
+    HIP_TRY(launch_frame_state(d->dom, d->parity, d->stream));
+    size_t plane = (size_t)frame_rows(d->p.ny) * d->dom.pitch * sizeof(float);
     HIP_TRY(hipMemcpyAsync(d->dom.eta1, d->dom.eta, plane, hipMemcpyDeviceToDevice, d->stream));
     HIP_TRY(hipMemcpyAsync(d->dom.hu1, d->dom.hu, plane, hipMemcpyDeviceToDevice, d->stream));
     HIP_TRY(hipMemcpyAsync(d->dom.hv1, d->dom.hv, plane, hipMemcpyDeviceToDevice, d->stream));
@@ -385,8 +393,8 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
 
     Dom &D = d->dom;
     D.nx = nx; D.ny = ny;
-    D.pitch = pitch_of(nx);
-    D.cpitch = pitch_of(nx + 1);
+    D.pitch = pitch_of(frame_cols(nx));
+    D.cpitch = pitch_of(frame_cols(nx) + 1);
     D.P = 2 * nx + 2 * ny;
     for (int k = 0; k < 4; ++k) D.bc[k] = p->bc[k];
     D.dx = (float)p->dx; D.dy = (float)p->dy;
@@ -447,10 +455,15 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
         Uploader up(s, (5 + (p->north_projection ? 1 : 0)) * (nk + 64 * (size_t)(ny + 1)) * sizeof(float));
         std::vector<float> th0;
         if (p->north_projection && !theta) th0.assign(nc, 0.f);
-        if ((e = up.plane(w + L.eta, D.pitch, eta, nx, ny)) || (e = up.plane(w + L.hu, D.pitch, hu, nx, ny)) ||
-            (e = up.plane(w + L.hv, D.pitch, hv, nx, ny)) || (e = up.plane(w + L.Hc, D.cpitch, Hc, nx + 1, ny + 1)) ||
-            (e = up.plane(w + L.f, D.pitch, fl.data(), nx, ny)) ||
-            (p->north_projection && (e = up.plane(w + L.north, D.pitch, theta ? theta : th0.data(), nx, ny))) ||
+        // the planes start at zero (frames and padding columns included);
+        // the interior cells and corners are uploaded at their frame origin
+        auto org = [&](size_t off) { return w + off + (2 * (size_t)D.pitch + 2) * sizeof(float); };
+        char *corg = w + L.Hc + (2 * (size_t)D.cpitch + 2) * sizeof(float);
+        if ((e = hipMemsetAsync(w + L.eta, 0, L.fghost - L.eta, s)) ||
+            (e = up.plane(org(L.eta), D.pitch, eta, nx, ny)) || (e = up.plane(org(L.hu), D.pitch, hu, nx, ny)) ||
+            (e = up.plane(org(L.hv), D.pitch, hv, nx, ny)) || (e = up.plane(corg, D.cpitch, Hc, nx + 1, ny + 1)) ||
+            (e = up.plane(org(L.f), D.pitch, fl.data(), nx, ny)) ||
+            (p->north_projection && (e = up.plane(org(L.north), D.pitch, theta ? theta : th0.data(), nx, ny))) ||
             (e = up.flush())) {
             delete d;
             return hip_fail(e, "upload");
@@ -472,7 +485,8 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
         return hip_fail(e, "upload");
     }
     D.nw = 1;
-    if ((r = copy_state_to_star(d)) || (r = reset_time_and_cfl(d, 0.0))) { delete d; return r; }
+    if ((e = launch_frame_static(D, s)) != hipSuccess) { delete d; return hip_fail(e, "frames"); }
+    if ((r = reset_time_and_cfl(d, 0.0)) || (r = copy_state_to_star(d))) { delete d; return r; }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) { delete d; return hip_fail(e, "init sync"); }
     *out = d;
     return SWE_OK;
@@ -501,9 +515,11 @@ int swe_set_forcing(swe_domain *d, int32_t kind, int32_t n_times, const double *
         if (!all_finite(data, n)) return fail(SWE_E_ARG, "non-finite boundary data");
         HIP_TRY(hipMemcpyAsync(w + d->L.bnd_t, times, n_times * sizeof(double), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(w + d->L.bnd, data, n * sizeof(float), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipStreamSynchronize(s));
         d->dom.nb = n_times;
         d->has_bnd = true;
+        // the nested ghosts of Q^n from the new boundary data
+        HIP_TRY(launch_frame_state(d->dom, d->parity, s));
+        HIP_TRY(hipStreamSynchronize(s));
     } else {
         return fail(SWE_E_ARG, "unknown forcing kind");
     }
@@ -694,7 +710,8 @@ int swe_read_state(swe_domain *d, float *eta, float *hu, float *hv, double *t, d
     if (!d) return fail(SWE_E_ARG, "domain is NULL");
     const int nx = d->p.nx, ny = d->p.ny;
     float *dst[3] = {eta, hu, hv};
-    float *src[3] = {d->dom.eta, d->dom.hu, d->dom.hv};
+    const size_t org = 2 * (size_t)d->dom.pitch + 2;  // cell (0, 0) of a framed plane
+    float *src[3] = {d->dom.eta + org, d->dom.hu + org, d->dom.hv + org};
     const size_t plane = (size_t)nx * ny;
     bool staged[3] = {false, false, false};
     for (int k = 0; k < 3; ++k) {
@@ -744,12 +761,14 @@ int swe_set_state(swe_domain *d, const float *eta, const float *hu, const float 
     {
         Uploader up(d->stream, 3 * nc * sizeof(float));
         hipError_t e;
-        if ((e = up.plane(d->dom.eta, d->dom.pitch, eta, nx, ny)) || (e = up.plane(d->dom.hu, d->dom.pitch, hu, nx, ny)) ||
-            (e = up.plane(d->dom.hv, d->dom.pitch, hv, nx, ny)) || (e = up.flush()))
+        const size_t org = 2 * (size_t)d->dom.pitch + 2;
+        if ((e = up.plane(d->dom.eta + org, d->dom.pitch, eta, nx, ny)) ||
+            (e = up.plane(d->dom.hu + org, d->dom.pitch, hu, nx, ny)) ||
+            (e = up.plane(d->dom.hv + org, d->dom.pitch, hv, nx, ny)) || (e = up.flush()))
             return hip_fail(e, "upload");
     }
-    if ((rc = copy_state_to_star(d)) ||
-        (rc = reset_time_and_cfl(d, t)))
+    if ((rc = reset_time_and_cfl(d, t)) ||
+        (rc = copy_state_to_star(d)))
         return rc;
     HIP_TRY(hipStreamSynchronize(d->stream));
     return SWE_OK;
@@ -1011,8 +1030,12 @@ int swe_autotune_tiling(swe_domain *d, int32_t *rows_per_wave)
     const int nx = d->p.nx, ny = d->p.ny;
     const size_t plane = (size_t)nx * ny;
     if ((rc = ensure_pinned_state(d))) return rc;
-    // the three value planes (float32) and the three rounding-error planes (16 bits)
-    void *q[6] = {d->dom.eta, d->dom.hu, d->dom.hv, d->dom.eta_lo, d->dom.hu_lo, d->dom.hv_lo};
+    // the three value planes (float32) and the three rounding-error planes
+    // (16 bits), from cell (0, 0) of each framed plane; the state frame is
+    // rebuilt afterwards
+    const size_t org = 2 * (size_t)d->dom.pitch + 2;
+    void *q[6] = {d->dom.eta + org, d->dom.hu + org, d->dom.hv + org, d->dom.eta_lo ? d->dom.eta_lo + org : nullptr,
+                  d->dom.hu_lo ? d->dom.hu_lo + org : nullptr, d->dom.hv_lo ? d->dom.hv_lo + org : nullptr};
     const int nq = d->p.compensated_state ? 6 : 3;
     auto esz = [](int k) { return k < 3 ? sizeof(float) : sizeof(uint16_t); };
     for (int k = 0; k < nq; ++k)
@@ -1031,6 +1054,7 @@ int swe_autotune_tiling(swe_domain *d, int32_t *rows_per_wave)
         HIP_TRY(hipMemcpy2DAsync(q[k], d->dom.pitch * esz(k), d->pinned_state + k * plane, nx * esz(k), nx * esz(k),
                                  ny, hipMemcpyHostToDevice, d->stream));
     HIP_TRY(hipMemcpyAsync(d->dom.ctrl, &saved, sizeof(Ctrl), hipMemcpyHostToDevice, d->stream));
+    HIP_TRY(launch_frame_state(d->dom, d->parity, d->stream));
     HIP_TRY(hipStreamSynchronize(d->stream));
     if (rc) return rc;
     d->T[0] = T1;

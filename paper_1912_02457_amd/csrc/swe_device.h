@@ -1,12 +1,20 @@
 // Device-side data structures of the gfx950 shallow-water stage kernels.
 //
 // One domain lives in a caller-provided device workspace:
-//   state Q^n (eta, hu, hv) and Q* as float32 planes [ny][pitch], pitch a
-//   multiple of 64 floats (256 B rows), the corner depths [ny+1][cpitch], the
-//   Coriolis plane f [ny][pitch] in which NaN marks a land cell (the static
-//   mask costs no extra bytes, as in the section "Moving wet-dry boundary and
-//   land mask"), small forcing tables and a control block holding the time,
-//   the CFL accumulators and the error flag.
+//   state Q^n (eta, hu, hv) and Q* as float32 planes, the corner depths, the
+//   Coriolis plane f in which NaN marks a land cell (the static mask costs no
+//   extra bytes, as in the section "Moving wet-dry boundary and land mask"),
+//   small forcing tables and a control block holding the time, the CFL
+//   accumulators and the error flag.
+//
+// Every plane carries a frame of kHalo ghost cells on each side, so that the
+// stage kernels read ghost cells like any other (no per-lane boundary logic
+// in the row loop): cell (i, r), -2 <= i < nx + 2 (and the padding columns
+// up to the last strip's reach), -2 <= r < ny + 2, is element
+// (r + 2) * pitch + (i + 2); corner (i, r), -2 <= i, r <= n + 2, is element
+// (r + 2) * cpitch + (i + 2) of the corner plane.  The frames of the static
+// planes (f, north angle, corner depths) are filled at init; those of Q^n
+// and Q* by the stage that writes the state, for the stage that reads it.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -75,7 +83,7 @@ inline double ctrl_next_dt(const Ctrl &c, int parity, float courant_q, double dt
 
 // Everything a stage kernel needs, passed by value.
 struct Dom {
-    int nx, ny, pitch, cpitch, P;  // P = 2 ny + 2 nx perimeter cells
+    int nx, ny, pitch, cpitch, P;  // P = 2 ny + 2 nx perimeter cells; pitches of the framed planes
     int bc[4];                     // W, E, S, N
     float dx, dy, rdx, rdy, kx, ky; // kx = dx / (2 g)
     float g, theta, kappa, inv2kappa, kappa_sq, courant_q; // courant_q = C / 4
@@ -86,11 +94,11 @@ struct Dom {
     double dt_interval;            // > 0: dt re-evaluated only once this much time has passed
     double g64, kappa64, dx64, dy64;  // float64 copies for the diagnostics reductions
     int frs_w;
-    float *eta, *hu, *hv;          // Q^n, updated in place by stage 2
+    float *eta, *hu, *hv;          // Q^n, updated in place by stage 2 (all planes: frame origin)
     float *eta1, *hu1, *hv1;       // Q*
     // compensated state (swe_params.compensated_state): the rounding error of
     // each stored value of Q^n and Q*, kept as the upper 16 bits of its
-    // float32 value (bfloat16, [ny][pitch]), so that value + error carries
+    // float32 value (bfloat16, framed like the state), so that value + error carries
     // the state to about 2^-10 of a float32 ulp; NULL when off
     uint16_t *eta_lo, *hu_lo, *hv_lo, *eta1_lo, *hu1_lo, *hv1_lo;
     const float *Hc, *f, *north;
@@ -111,6 +119,21 @@ struct Dom {
     Ctrl *ctrl;
     double *partials;              // diagnostics partial sums
 };
+
+// frame layout (see the top of this file)
+constexpr int kFrame = kHalo;
+__host__ __device__ inline uint32_t cell_off(const Dom &d, int r, int i)
+{
+    return (uint32_t)(r + kFrame) * (uint32_t)d.pitch + (uint32_t)(i + kFrame);
+}
+__host__ __device__ inline uint32_t corner_off(const Dom &d, int r, int i)
+{
+    return (uint32_t)(r + kFrame) * (uint32_t)d.cpitch + (uint32_t)(i + kFrame);
+}
+// columns a plane must hold: the lanes of the last 60-column strip reach
+// column 60 * nstrips + 1; corners one further
+__host__ __device__ inline int frame_cols(int nx) { return (nx + kStrip - 1) / kStrip * kStrip + 2 * kFrame; }
+__host__ __device__ inline int frame_rows(int ny) { return ny + 2 * kFrame; }
 
 struct Tiling {
     int by;       // rows per wave of the head bands

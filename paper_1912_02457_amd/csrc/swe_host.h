@@ -19,6 +19,8 @@ hipError_t launch_ensemble(int stage, bool proj, bool w10, bool comp, const EnsM
                            hipEvent_t ev1);
 hipError_t launch_cfl(const Dom &d, int slot, hipStream_t s);
 hipError_t launch_ctrl_reset(Ctrl *c, double t, int slot, hipStream_t s);
+hipError_t launch_frame_static(const Dom &d, hipStream_t s);
+hipError_t launch_frame_state(const Dom &d, int parity, hipStream_t s);
 hipError_t launch_set_t_end(Ctrl *c, double te, hipStream_t s);
 hipError_t launch_policy_reset(Ctrl *c, int parity, hipStream_t s);
 hipError_t launch_diagnostics(const Dom &d, hipStream_t s);

@@ -7,8 +7,8 @@
 // the adjacent lanes (cross-lane shuffles), neighbours along y from the rows
 // kept in registers, so every face flux is evaluated once and reused by the
 // two cells that share the face, and no LDS is needed.  Global loads are
-// 64-float (256 B) row segments.  Ghost cells are produced at load time from
-// the boundary kinds (no ghost kernel).
+// 64-float (256 B) row segments.  Ghost cells sit in a 2-cell frame around
+// every plane, written by the stage that produces the state (swe_device.h).
 //
 // Arithmetic follows the paper in float32 with two exact rewritings:
 //   * the rest-state pressure g R_f^2/2 with R_f = max(H_f, 0) is taken out
@@ -73,6 +73,9 @@ __device__ __forceinline__ float two_sum(float a, float b, float &err)
     err = (a - ap) + (b - bp);
     return s;
 }
+
+constexpr uint32_t kSign = 0x80000000u;
+__device__ __forceinline__ float flip_sign(float x, uint32_t s) { return __uint_as_float(__float_as_uint(x) ^ s); }
 
 // rounding errors of the own cell's stored Q^n (0) and Q* (1) values
 struct Lo {
@@ -262,7 +265,7 @@ __device__ __forceinline__ void positivity_fix(float e, float rho, float Hp, flo
 
 // One row of the sliding window (per lane: column i).
 struct Row {
-    float e, u, v, f;      // state (ghost-resolved) and Coriolis parameter (NaN: land)
+    float e, u, v, f;      // state and Coriolis parameter (NaN: land)
     float cx, cy;          // Coriolis terms of the reconstruction (f v, -f u)
     float Hw, He, Hs, Hn, Hb;
     float ri;              // 1 / h* of the cell
@@ -346,6 +349,10 @@ struct TileCtx {
     float dt, wx, wy;
     int bk;          // boundary snapshot interval and weight at the stage time
     double bs;
+    int fbk;         // the same at the time of the stage that reads this stage's output
+    double fbs;
+    bool edge;       // the tile writes ghost cells (output cells within two cells of a side)
+    int fca, fcb;    // ghost columns that copy this lane's cells (frame_copy_cols)
     int wk;          // wind-field snapshot interval and weight at the stage time
     float ws;
 };
@@ -429,9 +436,78 @@ __device__ __forceinline__ FrsPre frs_prefetch(const Dom &d, const TileCtx &c)
 // x-direction reconstruction and flux of the output row A, the update of
 // eq. rk2_semiimp and (stage 2) the flow relaxation and CFL reduction.
 // Every lane takes part in the cross-lane exchanges; only output lanes store.
-template <int STAGE, bool PROJ, bool FRS, bool W10, bool COMP>
+// Ghost cells of the state this stage writes (Q* in stage 1, Q^{n+1} in
+// stage 2) for the stage that reads it next, by edge tiles: the wall and
+// periodic copies of a water cell's new values (frame_copy_cols / _rows;
+// the lane's target columns are fixed for the tile, the row targets are
+// uniform), stored from the registers that hold them.  A land cell keeps
+// its state, and its ghosts their values.
+template <int STAGE>
+__device__ __forceinline__ void write_frame_copies(const Dom &d, const TileCtx &c, float e, float u, float v)
+{
+    float *__restrict__ E = STAGE == 1 ? d.eta1 : d.eta;
+    float *__restrict__ U = STAGE == 1 ? d.hu1 : d.hu;
+    float *__restrict__ V = STAGE == 1 ? d.hv1 : d.hv;
+    auto put = [&](int x, int y, float uu, float vv) {
+        const uint32_t o = cell_off(d, y, x);
+        st(E, o, e);
+        st(U, o, uu);
+        st(V, o, vv);
+    };
+    if (c.fca != kNoFrame) put(c.fca, c.o, d.bc[0] == BC_WALL ? -u : u, v);
+    if (c.fcb != kNoFrame) put(c.fcb, c.o, d.bc[1] == BC_WALL ? -u : u, v);
+    int ra, rb;
+    frame_copy_rows(d, c.o, ra, rb);
+    if (ra != kNoFrame) put(c.i, ra, u, d.bc[2] == BC_WALL ? -v : v);
+    if (rb != kNoFrame) put(c.i, rb, u, d.bc[3] == BC_WALL ? -v : v);
+}
+
+// Nested ghosts take the boundary data at the reading stage's time (the
+// interpolation of the boundary loads), independent of the state: written
+// after the row loop by the tiles next to a nested side, four rows at a
+// time so that their loads overlap.
+template <int STAGE>
+__device__ __forceinline__ void write_frame_nested(const Dom &d, const TileCtx &c, int y0, int y1)
+{
+    float *__restrict__ E = STAGE == 1 ? d.eta1 : d.eta;
+    float *__restrict__ U = STAGE == 1 ? d.hu1 : d.hu;
+    float *__restrict__ V = STAGE == 1 ? d.hv1 : d.hv;
+    const int nx = d.nx, ny = d.ny, x = c.i;
+    const uint32_t P = (uint32_t)d.P;
+    const float *__restrict__ ba = d.bnd + (uint32_t)c.fbk * 3u * P;
+    const float *__restrict__ bb = d.nb > 1 ? ba + 3u * P : ba;
+    const double t = c.fbs;
+    auto put = [&](int idx, int xa, int ya, int xb, int yb) {
+        const float e = (float)((1.0 - t) * (double)ba[idx] + t * (double)bb[idx]);
+        const float u = (float)((1.0 - t) * (double)ba[P + idx] + t * (double)bb[P + idx]);
+        const float v = (float)((1.0 - t) * (double)ba[2u * P + idx] + t * (double)bb[2u * P + idx]);
+        const uint32_t oa = cell_off(d, ya, xa), ob = cell_off(d, yb, xb);
+        st(E, oa, e); st(U, oa, u); st(V, oa, v);
+        st(E, ob, e); st(U, ob, u); st(V, ob, v);
+    };
+    // west / east: the lane of column 0 / nx-1, every row of the tile
+    const bool w = d.bc[0] == BC_NESTED && x == 0 && c.out_lane;
+    const bool e = d.bc[1] == BC_NESTED && x == nx - 1 && c.out_lane;
+    if (__ballot(w || e) != 0) {
+        for (int y = y0; y < y1; y += 4) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int yy = y + k;
+                if (yy < y1) {
+                    if (w) put(yy, -1, yy, -2, yy);
+                    if (e) put(ny + yy, nx, yy, nx + 1, yy);
+                }
+            }
+        }
+    }
+    // south / north: every output lane of row 0 / ny-1
+    if (d.bc[2] == BC_NESTED && y0 == 0 && c.out_lane) put(2 * ny + x, x, -1, x, -2);
+    if (d.bc[3] == BC_NESTED && y1 == ny && c.out_lane) put(2 * ny + nx + x, x, ny, x, ny + 1);
+}
+
+template <int STAGE, bool PROJ, bool W10, bool COMP>
 __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 &Gn, const TileCtx &c,
-                                           float e0, float u0, float v0, bool lo_ok, const FrsPre &fp,
+                                           float e0, float u0, float v0, const FrsPre &fp,
                                            const Dom &d, float &wmax_loc, int &bad)
 {
     const float th2 = d.theta2;
@@ -463,7 +539,7 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
 
     float Cx, Cy;
     if (PROJ) {
-        float ang = store ? ld(d.north, (uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i) : 0.f;
+        float ang = store ? ld(d.north, cell_off(d, c.o, c.i)) : 0.f;
         float cc = __cosf(ang), ss = __sinf(ang);
         float hue = cc * A.u - ss * A.v, hvn = ss * A.u + cc * A.v;
         Cx = A.f * (cc * hvn - ss * hue);
@@ -484,13 +560,13 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
                Cx + wx;
     float Mv = -(Fe.q - Fwq) * d.rdx - (Gn.p - Gs.p) * d.rdy +
                bathy_source(A.eN, A.eS, A.Hn, A.Hs, d) * d.rdy + Cy + wy;
-    const uint32_t oo = (uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i;
+    const uint32_t oo = cell_off(d, c.o, c.i);
     const float dt = c.dt;
     float S = friction_coeff(d, A.ri, A.u, A.v);
     // compensated: the stored rounding errors of the cell, loaded where they
     // are used (held across the row they would raise the register count)
     Lo lo{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (COMP && lo_ok) {
+    if (COMP) {
         lo.e0 = ld_lo(d.eta_lo, oo);
         lo.u0 = ld_lo(d.hu_lo, oo);
         lo.v0 = ld_lo(d.hv_lo, oo);
@@ -516,6 +592,7 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
                 st_lo(d.eta1_lo, oo, le);
                 st_lo(d.hu1_lo, oo, lu);
                 st_lo(d.hv1_lo, oo, lv);
+                if (c.edge) write_frame_copies<1>(d, c, en, un, vn);
             }
         } else {
             float en = A.e + dt * Me;
@@ -525,6 +602,7 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
                 st(d.eta1, oo, en);
                 st(d.hu1, oo, un);
                 st(d.hv1, oo, vn);
+                if (c.edge) write_frame_copies<1>(d, c, en, un, vn);
             }
         }
     } else {
@@ -544,7 +622,7 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
             un = 0.5f * (u0 + (A.u + dt * Mu)) * den;
             vn = 0.5f * (v0 + (A.v + dt * Mv)) * den;
         }
-        if (FRS && fp.zone) {
+        if (fp.zone) {
             // the boundary values are loaded here, where they are used, not
             // at the start of the row: held across the row they would raise
             // the register count of every tile's kernel
@@ -573,7 +651,9 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
                 st_lo(d.hu_lo, oo, lu);
                 st_lo(d.hv_lo, oo, lv);
             }
+            if (c.edge) write_frame_copies<2>(d, c, en, un, vn);
         }
+
         // eq. cfl on the new state
         float h = en + A.Hb;
         float ri = rcp(desing(h, d));
@@ -590,125 +670,56 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
 // ---- one tile: a wavefront's 64 columns over rows y0..y1-1 ------------------
 // The window of three rows rotates by unrolling (no register moves, no
 // per-row branches) and the next row is prefetched while the current one is
-// processed.  GHOST: the tile touches the domain edge, so loads go through
-// the boundary-kind mapping; otherwise plain 32-bit-offset loads.  FRS: the
-// tile has output cells inside a relaxation zone.
-// Raw loads of one row, issued one row ahead.  Ghost rows keep their sign
-// flips and, for nested ghosts, the second snapshot until the row is consumed
-// (finalize), so that the loads are not waited for where they are issued.
+// processed.  Every load is a plain 32-bit offset into a framed plane: the
+// ghost cells sit in the frame (filled by the stage that wrote the state),
+// so edge tiles load exactly as interior ones.  frs: the tile has output
+// cells inside a relaxation zone; edge: it has output cells within two
+// cells of a side, whose values it also writes into the frame afterwards.
 struct RawRow {
     float e, u, v, f, cn0, cn1, th;
-    float eb, ub, vb;  // nested ghosts: state at the later snapshot
-    uint32_t flip;     // sign bits to flip in hu (bit 31 of word 0), hv, f; bit 0: nested ghost
 };
 
-constexpr uint32_t kSign = 0x80000000u;
-__device__ __forceinline__ float flip_sign(float x, uint32_t s) { return __uint_as_float(__float_as_uint(x) ^ s); }
-
-template <bool PROJ, bool GHOST>
+template <bool PROJ>
 __device__ __forceinline__ RawRow load_row(const Dom &d, const float *__restrict__ E, const float *__restrict__ U,
-                                           const float *__restrict__ V, int il, const ColMap &cm, int r,
-                                           const TileCtx &c)
+                                           const float *__restrict__ V, int il, int r)
 {
     RawRow w;
-    w.flip = 0u;
-    w.eb = w.ub = w.vb = 0.f;
-    if (!GHOST) {
-        const uint32_t off = (uint32_t)r * (uint32_t)d.pitch + (uint32_t)il;
-        const uint32_t cof = (uint32_t)(r + 1) * (uint32_t)d.cpitch + (uint32_t)il;
-        w.e = ld(E, off);
-        w.u = ld(U, off);
-        w.v = ld(V, off);
-        w.f = ld(d.f, off);
-        w.cn0 = ld(d.Hc, cof);
-        w.cn1 = ld(d.Hc, cof + 1);
-        w.th = PROJ ? ld(d.north, off) : 0.f;
-    } else {
-        // A lane in a ghost column only ever contributes rows inside [0, ny);
-        // its rows outside (diagonal ghosts) load some in-bounds value that is
-        // never used.  (ghost_src in swe_maps.h computes the same sources for
-        // the host-side bounds check; kept inline here, where the register
-        // allocation of the kernels that hold it is tight.)
-        const RowMap rm = row_map(d, r);  // the same for all lanes
-        const bool yin = r >= 0 && r < d.ny;
-        int side = -1, idx = 0, layer = 0;
-        if (yin && cm.nside >= 0) {
-            side = cm.nside; layer = cm.nlayer; idx = cm.nside == 0 ? r : d.ny + r;
-        } else if (!yin && rm.nside >= 0) {
-            const int ii = imin(imax(il, 0), d.nx - 1);
-            side = rm.nside; layer = rm.nlayer; idx = rm.nside == 2 ? 2 * d.ny + ii : 2 * d.ny + d.nx + ii;
-        }
-        if (side >= 0) {
-            const uint32_t P = (uint32_t)d.P;
-            const float *a = d.bnd + (uint32_t)c.bk * 3u * P + (uint32_t)idx;
-            const float *b = d.nb > 1 ? a + 3u * P : a;
-            w.e = a[0]; w.u = a[P]; w.v = a[2u * P];
-            w.eb = b[0]; w.ub = b[P]; w.vb = b[2u * P];
-            w.flip = 1u;
-            w.f = d.fghost[(uint32_t)layer * P + (uint32_t)idx];
-            w.th = PROJ ? d.nghost[(uint32_t)layer * P + (uint32_t)idx] : 0.f;
-        } else {
-            const uint32_t off = (uint32_t)rm.cr * (uint32_t)d.pitch + (uint32_t)cm.ci;
-            w.e = ld(E, off);
-            w.u = ld(U, off);
-            w.v = ld(V, off);
-            w.f = ld(d.f, off);
-            // bits 31, 30, 29: flip hu, hv, f (a wall ghost negates them)
-            w.flip = (cm.su < 0.f ? kSign : 0u) | (rm.sv < 0.f ? kSign >> 1 : 0u) |
-                     ((cm.sf * rm.sf) < 0.f ? kSign >> 2 : 0u);
-            w.th = PROJ ? ld(d.north, off) : 0.f;
-        }
-        const uint32_t cof = (uint32_t)rm.crc * (uint32_t)d.cpitch;
-        w.cn0 = ld(d.Hc, cof + (uint32_t)cm.cc0);
-        w.cn1 = ld(d.Hc, cof + (uint32_t)cm.cc1);
-    }
+    const uint32_t off = cell_off(d, r, il);
+    const uint32_t cof = corner_off(d, r + 1, il);
+    w.e = ld(E, off);
+    w.u = ld(U, off);
+    w.v = ld(V, off);
+    w.f = ld(d.f, off);
+    w.cn0 = ld(d.Hc, cof);
+    w.cn1 = ld(d.Hc, cof + 1);
+    w.th = PROJ ? ld(d.north, off) : 0.f;
     return w;
 }
 
-template <int STAGE, bool PROJ, bool GHOST, bool FRS, bool W10, bool COMP>
-__device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1, float &wmax_loc, int &bad)
+template <int STAGE, bool PROJ, bool W10, bool COMP>
+__device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1, bool frs, bool edge, float &wmax_loc,
+                                         int &bad)
 {
     const float *__restrict__ E = STAGE == 1 ? d.eta : d.eta1;
     const float *__restrict__ U = STAGE == 1 ? d.hu : d.hu1;
     const float *__restrict__ V = STAGE == 1 ? d.hv : d.hv1;
-    const int il = GHOST ? min(c.i, d.nx + 1) : c.i;  // lanes right of the east ghosts load a ghost column
-    ColMap cm;
+    const int il = c.i;
     float cs0, cs1;  // south corners of the row loaded next
-    if (!GHOST) {
-        const uint32_t cof = (uint32_t)(y0 - 2) * (uint32_t)d.cpitch + (uint32_t)il;
+    {
+        const uint32_t cof = corner_off(d, y0 - 2, il);
         cs0 = ld(d.Hc, cof);
         cs1 = ld(d.Hc, cof + 1);
-    } else {
-        cm = col_map(d, il);
-        const uint32_t cof = (uint32_t)map_corner(y0 - 2, d.ny, d.bc[2], d.bc[3]) * (uint32_t)d.cpitch;
-        cs0 = ld(d.Hc, cof + (uint32_t)cm.cc0);
-        cs1 = ld(d.Hc, cof + (uint32_t)cm.cc1);
     }
     const int klast = y1 + 1;
-    RawRow nxt = load_row<PROJ, GHOST>(d, E, U, V, il, cm, y0 - 2, c);
+    RawRow nxt = load_row<PROJ>(d, E, U, V, il, y0 - 2);
 
     auto load = [&](Row &C, int k) {
         RawRow cur = nxt;
         // unconditional (the last row reloads itself), so that the memory
         // counter is the same on every path and a wait for this row's own
         // loads never has to drain the prefetch of the next one
-        nxt = load_row<PROJ, GHOST>(d, E, U, V, il, cm, min(k + 1, klast), c);
-        if (GHOST) {
-            if (cur.flip & 1u) {
-                const double t = c.bs;
-                C.e = (float)((1.0 - t) * (double)cur.e + t * (double)cur.eb);
-                C.u = (float)((1.0 - t) * (double)cur.u + t * (double)cur.ub);
-                C.v = (float)((1.0 - t) * (double)cur.v + t * (double)cur.vb);
-                C.f = cur.f;
-            } else {
-                C.e = cur.e;
-                C.u = flip_sign(cur.u, cur.flip & kSign);
-                C.v = flip_sign(cur.v, (cur.flip << 1) & kSign);
-                C.f = flip_sign(cur.f, (cur.flip << 2) & kSign);
-            }
-        } else {
-            C.e = cur.e; C.u = cur.u; C.v = cur.v; C.f = cur.f;
-        }
+        nxt = load_row<PROJ>(d, E, U, V, il, min(k + 1, klast));
+        C.e = cur.e; C.u = cur.u; C.v = cur.v; C.f = cur.f;
         row_terms<PROJ>(C, cs0, cs1, cur.cn0, cur.cn1, cur.th, d);
         cs0 = cur.cn0;
         cs1 = cur.cn1;
@@ -731,15 +742,15 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
     auto step = [&](Row &A, Row &B, Row &C, int k) {
         c.o = k - 2;
         float e0 = 0.f, u0 = 0.f, v0 = 0.f;
-        if (STAGE == 2 && (!GHOST || c.out_lane)) {
-            const uint32_t oq = (uint32_t)c.o * (uint32_t)d.pitch + (uint32_t)c.i;
+        if (STAGE == 2) {
+            const uint32_t oq = cell_off(d, c.o, c.i);
             e0 = ld(d.eta, oq);
             u0 = ld(d.hu, oq);
             v0 = ld(d.hv, oq);
         }
         FrsPre fp;
         fp.zone = false;
-        if (STAGE == 2 && FRS) {
+        if (STAGE == 2 && frs) {
             int best, dd;
             frs_side(d, c.i, c.o, best, dd);
             fp.zone = c.out_lane && best >= 0 && dd < d.frs_w;
@@ -751,7 +762,7 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
         F3 Gn = y_flux(A, B, us, vs, d);
         // a row whose output cells are all land has nothing to update
         if (__ballot(c.out_lane && !A.land) != 0)
-            finish_row<STAGE, PROJ, FRS, W10, COMP>(A, Gs, Gn, c, e0, u0, v0, !GHOST || c.out_lane, fp, d, wmax_loc, bad);
+            finish_row<STAGE, PROJ, W10, COMP>(A, Gs, Gn, c, e0, u0, v0, fp, d, wmax_loc, bad);
         Gs = Gn;
     };
     for (int k = y0 + 2;;) {
@@ -762,6 +773,7 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
         step(R1, R2, R0, k);
         if (++k > klast) break;
     }
+    if (edge) write_frame_nested<STAGE>(d, c, y0, y1);
 }
 
 // ---------------------------------------------------------------------------
@@ -771,6 +783,7 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
 // ---------------------------------------------------------------------------
 struct StepTime {
     double tn, dtd;
+    double tnext;       // time at the start of the next step
     double hold, tupd;  // dt update policy state after this step
     uint32_t wbits;
     bool skip, last;
@@ -804,6 +817,7 @@ __device__ __forceinline__ StepTime step_time(const Dom &d, int parity, double d
         if (s.tn >= te) s.skip = true;
         else if (s.dtd >= te - s.tn) { s.dtd = te - s.tn; s.last = true; }
     }
+    s.tnext = s.last ? te : s.tn + s.dtd;
     return s;
 }
 
@@ -821,7 +835,7 @@ __device__ __forceinline__ void advance_ctrl(Ctrl *ctrl, const StepTime &s, int 
         if (s.skip) {
             ctrl->t[parity ^ 1] = s.tn;
         } else {
-            ctrl->t[parity ^ 1] = s.last ? ctrl->t_end : s.tn + s.dtd;
+            ctrl->t[parity ^ 1] = s.tnext;
             ctrl->dt_last = (float)s.dtd;
             ctrl->steps += 1;
         }
@@ -861,10 +875,10 @@ __device__ __forceinline__ void process_tile(const Dom &d, const Tiling &T, int 
     c.o = y0;
     c.out_lane = lane >= kHalo && lane < kWave - kHalo && c.i < nx;
 
-    // ghost: some of columns x0-2 .. x0+61, rows y0-2 .. y1+1 or corner rows
-    // up to y1+2 fall outside the domain.  frs: some output cell lies within
-    // the relaxation zone of a nested side.
-    const bool ghost = !(x0 >= kHalo && x0 + kStrip + kHalo <= nx && y0 >= kHalo && y1 + kHalo <= ny);
+    // edge: some output cell lies within two cells of a side (its values go
+    // into the frame too).  frs: some output cell lies within the relaxation
+    // zone of a nested side.
+    const bool edge = x0 < kHalo || x0 + kStrip > nx - kHalo || y0 < kHalo || y1 > ny - kHalo;
     const int W = d.frs_w;
     bool frs = false;
     if (W > 0) {
@@ -873,12 +887,19 @@ __device__ __forceinline__ void process_tile(const Dom &d, const Tiling &T, int 
         frs |= d.bc[2] == BC_NESTED && y0 < W;
         frs |= d.bc[3] == BC_NESTED && y1 > ny - W;
     }
+    // nested frame cells are written for the time of the stage that reads
+    // them: stage 2 of this step, or stage 1 of the next
+    c.fbk = 0;
+    c.fbs = 0.0;
+    c.edge = edge;
+    frame_copy_cols(d, c.i, c.fca, c.fcb);
+    if (edge && d.nb > 0) time_weights(d.nb, d.bnd_t, STAGE == 1 ? st.tn + st.dtd : st.tnext, c.fbk, c.fbs);
     float wmax_loc = 0.f;
     int bad = 0;
-    if (!ghost && !frs) run_tile<STAGE, PROJ, false, false, W10, COMP>(d, c, y0, y1, wmax_loc, bad);
-    else if (!ghost) run_tile<STAGE, PROJ, false, true, W10, COMP>(d, c, y0, y1, wmax_loc, bad);
-    else if (!frs) run_tile<STAGE, PROJ, true, false, W10, COMP>(d, c, y0, y1, wmax_loc, bad);
-    else run_tile<STAGE, PROJ, true, true, W10, COMP>(d, c, y0, y1, wmax_loc, bad);
+    // one row loop for every tile (a second variant of it in the same kernel
+    // raised the register count of both by ~25 VGPRs): the relaxation zone
+    // and the frame writes are uniform branches
+    run_tile<STAGE, PROJ, W10, COMP>(d, c, y0, y1, frs, edge, wmax_loc, bad);
 
     if (STAGE == 2) {
         wmax_loc = wave_max(wmax_loc);
@@ -919,13 +940,13 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void stage_kernel(Dom d, Ti
 // chunks taken with one atomicAdd each, until the partition is exhausted.
 // Every member has its own parameters, time, dt slot and CFL accumulator.
 // ---------------------------------------------------------------------------
-// Four waves per SIMD for the plain and the compensated-state variants (the
-// compensated one then spills a few words outside its row loop, measured
-// about 3 % faster on the 256-member ensemble than at three waves without
-// spills); the literal-projection and gridded-wind variants keep the
-// compiler's choice.
+// Four waves per SIMD for the plain variant (128 VGPRs); the others keep
+// the compiler's choice: capped at four, the compensated stage 1 ran 23 %
+// slower with the frame copies of its edge items (A/B on the 256-member
+// workload at fixed tiles), and the literal-projection and gridded-wind
+// variants would spill.
 template <int STAGE, bool PROJ, bool W10, bool COMP>
-__global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu((PROJ || W10) ? 1 : 4)))
+__global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu((PROJ || W10 || COMP) ? 1 : 4)))
 void ensemble_kernel(const EnsMember *__restrict__ mem,
                                                                          const EnsItem *__restrict__ items,
                                                                          EnsCtrl *ec, int parity, int chunk)
@@ -969,9 +990,9 @@ __global__ void cfl_kernel(Dom d, int slot)
     float w = 0.f;
     int bad = 0;
     if (i < d.nx && j < d.ny) {
-        size_t o = (size_t)j * d.pitch + i;
+        const size_t o = cell_off(d, j, i);
         if (!isnan(d.f[o])) {
-            const float *H0 = d.Hc + (size_t)j * d.cpitch, *H1 = H0 + d.cpitch;
+            const float *H0 = d.Hc + corner_off(d, j, 0), *H1 = H0 + d.cpitch;
             float Hb = 0.25f * ((H0[i] + H1[i]) + (H0[i + 1] + H1[i + 1]));
             float e = d.eta[o], u = d.hu[o], v = d.hv[o];
             float h = e + Hb;
@@ -989,6 +1010,74 @@ __global__ void cfl_kernel(Dom d, int slot)
         atomicMax(&d.ctrl->wslot[slot][k][0], __float_as_uint(w));
         if (fl) atomicOr(&d.ctrl->flags, fl);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Frames filled on the host side of the library's calls (init, a new state,
+// new boundary data): the static planes (f, north angle, corner depths), and
+// the frame of Q^n for the time of the step of a parity.  Afterwards the
+// stage kernels keep the state frames current.  Every source is an interior
+// cell or corner (col_map / row_map / map_corner), every target a frame cell,
+// so no thread reads what another writes.
+// ---------------------------------------------------------------------------
+__global__ void frame_static_kernel(Dom d)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncell = frame_cells(d);
+    float *f = const_cast<float *>(d.f), *north = const_cast<float *>(d.north), *Hc = const_cast<float *>(d.Hc);
+    if (k < ncell) {
+        int x, y;
+        frame_cell(d, k, x, y);
+        const GhostSrc g = ghost_src(d, col_map(d, x), x, y);
+        float fv, th = 0.f;
+        if (g.side >= 0) {
+            const uint32_t q = (uint32_t)g.layer * (uint32_t)d.P + (uint32_t)g.idx;
+            fv = d.fghost[q];
+            if (north) th = d.nghost[q];
+        } else {
+            fv = flip_sign(f[g.off], (g.flip << 2) & kSign);
+            if (north) th = north[g.off];
+        }
+        const uint32_t o = cell_off(d, y, x);
+        f[o] = fv;
+        if (north) north[o] = th;
+    } else if (k < ncell + frame_corners(d)) {
+        int x, y;
+        frame_corner(d, k - ncell, x, y);
+        const int cx = map_corner(x, d.nx, d.bc[0], d.bc[1]), cy = map_corner(y, d.ny, d.bc[2], d.bc[3]);
+        Hc[corner_off(d, y, x)] = Hc[corner_off(d, cy, cx)];
+    }
+}
+
+__global__ void frame_state_kernel(Dom d, int parity)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= frame_cells(d)) return;
+    int x, y;
+    frame_cell(d, k, x, y);
+    const GhostSrc g = ghost_src(d, col_map(d, x), x, y);
+    float e = 0.f, u = 0.f, v = 0.f;
+    if (g.side >= 0) {
+        if (d.nb > 0) {  // the interpolation of the stage kernels' boundary loads
+            int bk;
+            double t;
+            time_weights(d.nb, d.bnd_t, d.ctrl->t[parity], bk, t);
+            const uint32_t P = (uint32_t)d.P;
+            const float *pa = d.bnd + (uint32_t)bk * 3u * P + (uint32_t)g.idx;
+            const float *pb = d.nb > 1 ? pa + 3u * P : pa;
+            e = (float)((1.0 - t) * (double)pa[0] + t * (double)pb[0]);
+            u = (float)((1.0 - t) * (double)pa[P] + t * (double)pb[P]);
+            v = (float)((1.0 - t) * (double)pa[2u * P] + t * (double)pb[2u * P]);
+        }
+    } else {
+        e = d.eta[g.off];
+        u = flip_sign(d.hu[g.off], g.flip & kSign);
+        v = flip_sign(d.hv[g.off], (g.flip << 1) & kSign);
+    }
+    const uint32_t o = cell_off(d, y, x);
+    d.eta[o] = e;
+    d.hu[o] = u;
+    d.hv[o] = v;
 }
 
 // control block set-up: time, CFL slot cleared, flags cleared
@@ -1036,9 +1125,9 @@ __global__ __launch_bounds__(kDiagThreads) void diag_partial_kernel(Dom d)
     double m = 0.0, en = 0.0;
     const double area = d.dx64 * d.dy64;
     for (int i = threadIdx.x; i < d.nx; i += kDiagThreads) {
-        size_t o = (size_t)j * d.pitch + i;
+        const size_t o = cell_off(d, j, i);
         if (isnan(d.f[o])) continue;
-        const float *H0 = d.Hc + (size_t)j * d.cpitch, *H1 = H0 + d.cpitch;
+        const float *H0 = d.Hc + corner_off(d, j, 0), *H1 = H0 + d.cpitch;
         double Hb = 0.25 * ((double)H0[i] + (double)H0[i + 1] + (double)H1[i] + (double)H1[i + 1]);
         double e = d.eta[o], u = d.hu[o], v = d.hv[o];
         double h = e + Hb;
@@ -1192,6 +1281,20 @@ hipError_t launch_cfl(const Dom &d, int slot, hipStream_t s)
 {
     dim3 grid((d.nx + 255) / 256, d.ny), block(256);
     cfl_kernel<<<grid, block, 0, s>>>(d, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_frame_static(const Dom &d, hipStream_t s)
+{
+    const int n = frame_cells(d) + frame_corners(d);
+    hipLaunchKernelGGL(frame_static_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_frame_state(const Dom &d, int parity, hipStream_t s)
+{
+    const int n = frame_cells(d);
+    hipLaunchKernelGGL(frame_state_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, parity);
     return hipGetLastError();
 }
 

@@ -16,6 +16,8 @@ hipError_t launch_ensemble(int, bool, bool, bool, const EnsMember *, const EnsIt
 }
 hipError_t launch_cfl(const Dom &, int, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_ctrl_reset(Ctrl *, double, int, hipStream_t) { return hipErrorNoDevice; }
+hipError_t launch_frame_static(const Dom &, hipStream_t) { return hipErrorNoDevice; }
+hipError_t launch_frame_state(const Dom &, int, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_set_t_end(Ctrl *, double, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_policy_reset(Ctrl *, int, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_diagnostics(const Dom &, hipStream_t) { return hipErrorNoDevice; }

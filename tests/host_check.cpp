@@ -2,17 +2,23 @@
 // runs, built with AddressSanitizer and UndefinedBehaviorSanitizer by
 // tests/test_host_sanitized.py (no GPU needed):
 //
-//  1. every element a stage kernel reads or writes lies inside its plane or
-//     table: for each tile of every tiling the tuner can pick (one and two
-//     band heights, four tile orders) of domains from 2 x 2 up, under every
-//     combination of boundary kinds, the state and corner offsets of the
-//     plain path, the ghost sources (swe_maps.h: ghost_src, col_map,
-//     row_map, map_corner -- the functions and composition the kernels
-//     use), the own-cell loads and stores, the boundary-table and ghost
-//     tables of nested sides, and the relaxation-zone entries;
-//  2. at the largest domain the library accepts, the 32-bit element offsets
+//  1. every element a stage kernel reads or writes lies inside its framed
+//     plane or table: for each tile of every tiling the tuner can pick (one
+//     and two band heights, four tile orders) of domains from 2 x 2 up,
+//     under every combination of boundary kinds, the row and corner loads,
+//     the own-cell loads and stores, the frame writes of edge tiles
+//     (swe_maps.h: for_frame_targets), the boundary-table entries of nested
+//     ghosts and the relaxation-zone entries;
+//  2. the frames: the cells the stage kernels write for the next stage are
+//     exactly the frame cells an output depends on (the ghost columns next to
+//     rows 0 .. ny-1 and the ghost rows next to columns 0 .. nx-1), each
+//     written once, with the source and sign flips (or boundary entry) that
+//     the library's frame fill takes for it (ghost_src); the fill's
+//     enumerations of frame cells and frame corners cover each exactly once
+//     and read only interior cells and corners;
+//  3. at the largest domain the library accepts, the 32-bit element offsets
 //     equal the exact ones (no wrap-around);
-//  3. the serving loop's arena allocator (swe_arena.h) under random
+//  4. the serving loop's arena allocator (swe_arena.h) under random
 //     allocate / release sequences: blocks are aligned, never overlap each
 //     other or the free list, the free list stays coalesced, used + free
 //     equals the size, and releasing everything leaves one free block.
@@ -22,7 +28,10 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <random>
+#include <set>
+#include <utility>
 #include <vector>
 
 using namespace swe;
@@ -39,23 +48,27 @@ static long g_bad = 0;
 
 static int pitch_of(int n) { return (n + 63) / 64 * 64; }
 
+// the layout of swe_api.hip's make_layout
 static Dom make_dom(int nx, int ny, const int bc[4], int frs_w)
 {
     Dom d{};
     d.nx = nx; d.ny = ny;
-    d.pitch = pitch_of(nx);
-    d.cpitch = pitch_of(nx + 1);
+    d.pitch = pitch_of(frame_cols(nx));
+    d.cpitch = pitch_of(frame_cols(nx) + 1);
     d.P = 2 * nx + 2 * ny;
     for (int k = 0; k < 4; ++k) d.bc[k] = bc[k];
     d.frs_w = frs_w;
     return d;
 }
 
+static uint64_t plane_elems(const Dom &d) { return (uint64_t)frame_rows(d.ny) * d.pitch; }
+static uint64_t corner_elems(const Dom &d) { return (uint64_t)(frame_rows(d.ny) + 1) * d.cpitch; }
+
 // every access of one stage launch under tiling T (nb boundary snapshots)
 static void check_tiling(const Dom &d, const Tiling &T, int nb)
 {
     const int nx = d.nx, ny = d.ny;
-    const uint64_t plane = (uint64_t)ny * d.pitch, cplane = (uint64_t)(ny + 1) * d.cpitch;
+    const uint64_t plane = plane_elems(d), cplane = corner_elems(d);
     const uint64_t P = (uint64_t)d.P;
     const uint64_t bnd_elems = (uint64_t)(nb > 0 ? nb : 1) * 3 * P;
     for (int b = 0; b < T.nblocks; ++b)
@@ -65,49 +78,39 @@ static void check_tiling(const Dom &d, const Tiling &T, int nb)
             int strip, y0, y1;
             tile_place(T, tile, ny, strip, y0, y1);
             const int x0 = strip * kStrip;
-            const bool ghost = !(x0 >= kHalo && x0 + kStrip + kHalo <= nx && y0 >= kHalo && y1 + kHalo <= ny);
+            const bool edge = x0 < kHalo || x0 + kStrip > nx - kHalo || y0 < kHalo || y1 > ny - kHalo;
             const int klast = y1 + 1;
             for (int lane = 0; lane < kWave; ++lane) {
                 const int i = x0 - kHalo + lane;
                 const bool out_lane = lane >= kHalo && lane < kWave - kHalo && i < nx;
-                if (!ghost) {
-                    CHECK(i >= 0 && i < nx, "plain tile column %d of %dx%d", i, nx, ny);
-                    const uint64_t c0 = (uint64_t)(y0 - 2) * d.cpitch + (uint64_t)i;
-                    CHECK(y0 - 2 >= 0 && c0 + 1 < cplane, "first corner row, tile %d", tile);
-                    for (int k = y0 - 2; k <= klast; ++k) {
-                        CHECK(k >= 0 && (uint64_t)k * d.pitch + (uint64_t)i < plane, "row %d col %d", k, i);
-                        CHECK((uint64_t)(k + 1) * d.cpitch + (uint64_t)i + 1 < cplane, "corner row %d", k + 1);
-                    }
-                } else {
-                    const int il = imin(i, nx + 1);
-                    const ColMap cm = col_map(d, il);
-                    CHECK(cm.cc0 >= 0 && cm.cc0 <= nx && cm.cc1 >= 0 && cm.cc1 <= nx, "corner cols %d %d", cm.cc0,
-                          cm.cc1);
-                    const int c0r = map_corner(y0 - 2, ny, d.bc[2], d.bc[3]);
-                    CHECK(c0r >= 0 && c0r <= ny, "first corner row %d", c0r);
-                    for (int k = y0 - 2; k <= klast; ++k) {
-                        const GhostSrc g = ghost_src(d, cm, il, k);
-                        if (g.side >= 0) {
-                            CHECK(nb >= 1, "nested ghost without boundary snapshots");
-                            CHECK(g.idx >= 0 && (uint64_t)g.idx < P && g.layer >= 0 && g.layer < 2,
-                                  "boundary entry %d layer %d", g.idx, g.layer);
-                            for (int bk = 0; bk <= (nb > 1 ? nb - 2 : 0); ++bk) {
-                                const uint64_t a = (uint64_t)bk * 3 * P + (uint64_t)g.idx;
-                                const uint64_t last = a + 2 * P + (nb > 1 ? 3 * P : 0);
-                                CHECK(last < bnd_elems, "boundary snapshot element %llu", (unsigned long long)last);
-                            }
-                            CHECK((uint64_t)g.layer * P + (uint64_t)g.idx < 2 * P, "ghost-table entry");
-                        } else {
-                            CHECK(g.off < plane, "ghost source %u of %llu (row %d col %d)", g.off,
-                                  (unsigned long long)plane, k, il);
-                        }
-                        CHECK(g.cof0 < cplane && g.cof1 < cplane, "ghost corners %u %u", g.cof0, g.cof1);
-                    }
+                CHECK(i >= -kFrame && (uint64_t)(i + kFrame) < (uint64_t)d.pitch, "column %d of %dx%d", i, nx, ny);
+                CHECK(corner_off(d, y0 - 2, i) + 1 < cplane, "first corner row, tile %d", tile);
+                for (int k = y0 - 2; k <= klast; ++k) {
+                    CHECK(k >= -kFrame && cell_off(d, k, i) < plane, "row %d col %d", k, i);
+                    CHECK(corner_off(d, k + 1, i) + 1 < cplane, "corner row %d", k + 1);
                 }
-                if (!out_lane) continue;
                 for (int o = y0; o < y1; ++o) {
-                    // own-cell loads and stores of the update
-                    CHECK(i >= 0 && (uint64_t)o * d.pitch + (uint64_t)i < plane, "own cell %d %d", o, i);
+                    // own-cell loads (every lane) and stores (output lanes)
+                    CHECK(cell_off(d, o, i) < plane, "own cell %d %d", o, i);
+                    if (!out_lane) continue;
+                    if (edge)
+                        for_frame_targets(d, i, o, [&](int xx, int yy, uint32_t, int idx) {
+                            CHECK(xx >= -kFrame && xx < nx + kFrame && yy >= -kFrame && yy < ny + kFrame,
+                                  "frame target %d %d", xx, yy);
+                            CHECK(cell_off(d, yy, xx) < plane, "frame target offset");
+                            if (idx >= 0) {
+                                CHECK(nb >= 1, "nested frame without boundary snapshots");
+                                CHECK((uint64_t)idx < P, "boundary entry %d", idx);
+                                for (int bk = 0; bk <= (nb > 1 ? nb - 2 : 0); ++bk) {
+                                    const uint64_t last = (uint64_t)bk * 3 * P + (uint64_t)idx + 2 * P + (nb > 1 ? 3 * P : 0);
+                                    CHECK(last < bnd_elems, "boundary snapshot element %llu", (unsigned long long)last);
+                                }
+                            }
+                        });
+                    else
+                        for_frame_targets(d, i, o, [&](int, int, uint32_t, int) {
+                            CHECK(false, "interior tile cell %d %d has frame targets", i, o);
+                        });
                     // relaxation zone
                     if (d.frs_w > 0) {
                         int best, dd;
@@ -125,11 +128,83 @@ static void check_tiling(const Dom &d, const Tiling &T, int nb)
         }
 }
 
+// the frame cells written by the stages, against the frame cells an output
+// depends on and against the library's frame fill (ghost_src)
+static void check_frames(const Dom &d)
+{
+    const int nx = d.nx, ny = d.ny;
+    std::map<std::pair<int, int>, int> seen;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            for_frame_targets(d, x, y, [&](int xx, int yy, uint32_t flip, int idx) {
+                ++seen[std::make_pair(xx, yy)];
+                const GhostSrc g = ghost_src(d, col_map(d, xx), xx, yy);
+                if (idx >= 0) {
+                    CHECK(g.side >= 0 && g.idx == idx, "nested frame (%d, %d): fill entry %d, stage entry %d", xx, yy,
+                          g.idx, idx);
+                } else {
+                    CHECK(g.side < 0 && g.off == cell_off(d, y, x), "frame (%d, %d): fill source differs from (%d, %d)",
+                          xx, yy, x, y);
+                    CHECK((g.flip & 0xC0000000u) == flip, "frame (%d, %d): sign flips %x vs %x", xx, yy, g.flip, flip);
+                }
+            });
+    // the frame cells an output depends on: ghost columns beside rows 0 .. ny-1,
+    // ghost rows beside columns 0 .. nx-1; each written exactly once
+    size_t want = 0;
+    auto times = [&](int x, int y) {
+        const auto it = seen.find(std::make_pair(x, y));
+        return it == seen.end() ? 0 : it->second;
+    };
+    for (int y = 0; y < ny; ++y)
+        for (int xx : {-2, -1, nx, nx + 1}) {
+            ++want;
+            const int n = times(xx, y);
+            CHECK(n == 1, "ghost column cell (%d, %d) written %d times (%dx%d, bc %d%d%d%d)", xx, y, n, nx, ny, d.bc[0],
+                  d.bc[1], d.bc[2], d.bc[3]);
+        }
+    for (int x = 0; x < nx; ++x)
+        for (int yy : {-2, -1, ny, ny + 1}) {
+            ++want;
+            const int n = times(x, yy);
+            CHECK(n == 1, "ghost row cell (%d, %d) written %d times", x, yy, n);
+        }
+    CHECK(seen.size() == want, "%zu frame cells written, %zu expected", seen.size(), want);
+    // the fill's enumerations: each frame cell / corner once, interior sources
+    std::set<std::pair<int, int>> cells, corners;
+    for (int k = 0; k < frame_cells(d); ++k) {
+        int x, y;
+        frame_cell(d, k, x, y);
+        CHECK(x >= -2 && x < nx + 2 && y >= -2 && y < ny + 2 && !(x >= 0 && x < nx && y >= 0 && y < ny),
+              "frame cell %d -> (%d, %d)", k, x, y);
+        cells.insert(std::make_pair(x, y));
+        const GhostSrc g = ghost_src(d, col_map(d, x), x, y);
+        if (g.side < 0) {
+            const RowMap rm = row_map(d, y);
+            const ColMap cm = col_map(d, x);
+            CHECK(rm.cr >= 0 && rm.cr < ny && cm.ci >= 0 && cm.ci < nx, "frame (%d, %d) source (%d, %d)", x, y, cm.ci, rm.cr);
+        } else {
+            CHECK(g.idx >= 0 && g.idx < d.P && g.layer >= 0 && g.layer < 2, "frame (%d, %d) entry %d", x, y, g.idx);
+        }
+    }
+    CHECK((int)cells.size() == (nx + 4) * (ny + 4) - nx * ny, "frame cells enumerated %zu", cells.size());
+    for (int k = 0; k < frame_corners(d); ++k) {
+        int x, y;
+        frame_corner(d, k, x, y);
+        CHECK(x >= -2 && x <= nx + 2 && y >= -2 && y <= ny + 2 && !(x >= 0 && x <= nx && y >= 0 && y <= ny),
+              "frame corner %d -> (%d, %d)", k, x, y);
+        corners.insert(std::make_pair(x, y));
+        const int cx = map_corner(x, nx, d.bc[0], d.bc[1]), cy = map_corner(y, ny, d.bc[2], d.bc[3]);
+        CHECK(cx >= 0 && cx <= nx && cy >= 0 && cy <= ny, "corner (%d, %d) source (%d, %d)", x, y, cx, cy);
+    }
+    CHECK((int)corners.size() == (nx + 5) * (ny + 5) - (nx + 1) * (ny + 1), "frame corners enumerated %zu",
+          corners.size());
+}
+
 static void check_maps()
 {
     const int nxs[] = {2, 3, 5, 60, 61, 62, 63, 65, 121, 257};
     const int nys[] = {2, 3, 5, 7, 16, 33, 100};
-    long cases = 0;
+    long cases = 0, frames = 0;
     for (int nx : nxs)
         for (int ny : nys)
             for (int bx = 0; bx < 3; ++bx)
@@ -141,6 +216,8 @@ static void check_maps()
                         bc[2] = byk; bc[3] = byk == BC_PERIODIC ? BC_PERIODIC : (mixed ? (byk == BC_WALL ? BC_NESTED : BC_WALL) : byk);
                         const bool nested = bc[0] == BC_NESTED || bc[1] == BC_NESTED || bc[2] == BC_NESTED || bc[3] == BC_NESTED;
                         const Dom d = make_dom(nx, ny, bc, nested ? 10 : 0);
+                        check_frames(d);
+                        ++frames;
                         for (int nb : {1, 3}) {
                             if (!nested && nb > 1) continue;
                             for (int by = 1; by <= 24; by += (by < 8 ? 1 : 5))
@@ -153,38 +230,32 @@ static void check_maps()
                                     }
                         }
                     }
-    printf("maps: %ld tilings checked\n", cases);
+    printf("maps: %ld tilings and %ld frame layouts checked\n", cases, frames);
 }
 
-// 32-bit element offsets at the largest domain the library accepts (its
-// corner plane just below 4 GiB): equal to the exact 64-bit ones
+// 32-bit element offsets at the largest domains the library accepts (the
+// framed corner plane just below 4 GiB): equal to the exact 64-bit ones
 static void check_offsets_largest()
 {
     const int bc[4] = {BC_NESTED, BC_WALL, BC_PERIODIC, BC_PERIODIC};
-    // nx, ny with (ny + 1) * pitch(nx + 1) * 4 < 2^32
-    const int shapes[][2] = {{16384, 16384}, {32767, 32000}, {65535, 16000}, {2, 500000000}};
+    const int shapes[][2] = {{16384, 16384}, {32700, 32000}, {65500, 16000}, {2, 500000000}};
     for (auto &s : shapes) {
         const int nx = s[0], ny = s[1];
-        if ((uint64_t)(ny + 1) * pitch_of(nx + 1) * 4 >= ((uint64_t)1 << 32)) continue;
+        if ((uint64_t)(frame_rows(ny) + 1) * pitch_of(frame_cols(nx) + 1) * 4 >= ((uint64_t)1 << 32)) continue;
         const Dom d = make_dom(nx, ny, bc, 10);
-        const int cols[] = {-2, -1, 0, 1, nx / 2, nx - 1, nx, nx + 1};
+        const int cols[] = {-2, -1, 0, 1, nx / 2, nx - 1, nx, nx + 1, frame_cols(nx) - 3};
         const int rows[] = {-2, -1, 0, 1, ny / 2, ny - 2, ny - 1, ny, ny + 1};
         for (int c : cols)
             for (int r : rows) {
-                const ColMap cm = col_map(d, c);
-                const RowMap rm = row_map(d, r);
-                const GhostSrc g = ghost_src(d, cm, c, r);
-                if (g.side < 0) {
-                    const uint64_t exact = (uint64_t)rm.cr * (uint64_t)d.pitch + (uint64_t)cm.ci;
-                    CHECK(exact == g.off && exact < ((uint64_t)1 << 30), "offset wraps at %dx%d (%d, %d)", nx, ny, c, r);
-                }
-                const uint64_t ce = (uint64_t)rm.crc * (uint64_t)d.cpitch + (uint64_t)cm.cc1;
-                CHECK(ce == g.cof1 && ce < ((uint64_t)1 << 30), "corner offset wraps at %dx%d", nx, ny);
+                const uint64_t exact = (uint64_t)(r + 2) * (uint64_t)d.pitch + (uint64_t)(c + 2);
+                CHECK(exact == cell_off(d, r, c) && exact < plane_elems(d) && (exact << 2) < ((uint64_t)1 << 32),
+                      "cell offset wraps at %dx%d (%d, %d)", nx, ny, c, r);
+                const uint64_t ce = (uint64_t)(r + 3) * (uint64_t)d.cpitch + (uint64_t)(c + 3);
+                CHECK(ce == corner_off(d, r + 1, c + 1) && ce < corner_elems(d) && (ce << 2) < ((uint64_t)1 << 32),
+                      "corner offset wraps at %dx%d", nx, ny);
+                const GhostSrc g = ghost_src(d, col_map(d, c), c, r);
+                CHECK(g.cof1 < corner_elems(d), "ghost corner beyond the plane at %dx%d", nx, ny);
             }
-        // the plain path's row offset at the last row and column
-        const uint64_t last = (uint64_t)(ny - 1) * d.pitch + (uint64_t)(nx - 1);
-        CHECK((uint32_t)((uint32_t)(ny - 1) * (uint32_t)d.pitch + (uint32_t)(nx - 1)) == last, "row offset wraps");
-        CHECK((last << 2) < ((uint64_t)1 << 32), "byte offset of a plane element beyond 4 GiB");
     }
     printf("offsets: largest domains checked\n");
 }

@@ -91,6 +91,8 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run warmup + this many steps (for rocprofv3 runs), no JSON")
     ap.add_argument("--no-preprocess", action="store_true")
+    ap.add_argument("--no-full-length", action="store_true",
+                    help="skip the full-step-count parity of configs 2 and 3 against the stored oracle results")
     ap.add_argument("--no-strip", action="store_true", help="skip the one-strip-of-8 measurement")
     ap.add_argument("--no-sweep", action="store_true", help="skip the domain-size sweep")
     ap.add_argument("--sweep-max", type=int, default=8192,
@@ -524,6 +526,41 @@ def bench_sweep(a, np, torch):
             "note": "paper_run_s = N steps (1600 s at dt = 1600/N) at the measured rate; "
                     "paper_p100_total_s is the paper's Tesla P100 total (context, other hardware); "
                     "download_s = best of 3 copies of eta, hu, hv into pinned host memory (swe_read_state)"}
+
+
+def full_length_parity(torch):
+    """The benchmarked path over a configuration's full step count, each side
+    with its own CFL dt every step, against the oracle's stored final state
+    (tests/golden): config 2 (the NorKyst-sized hour, both state kinds) and
+    config 3 (the wet-dry beach, 5000 steps).  The bar: 1e-4 relative L2 and
+    5e-4 relative Linf per field; tests/test_gpu_full_length.py runs every
+    configuration, also with the oracle's dt sequence."""
+    from paper_1912_02457_amd import Domain
+    gdir = os.path.join(ROOT, "tests", "golden")
+    if gdir not in sys.path:
+        sys.path.insert(0, gdir)
+    import make_golden as MG
+    out = {}
+    for name, kinds in (("config2", (True, False)), ("config3", (True,))):
+        g = golden_state(name)
+        if g is None:
+            continue
+        ref, land = g
+        wl = MG.workload(name)
+        for comp in kinds:
+            d = Domain.from_workload(wl, device="cuda:0", compensated_state=comp)
+            if wl.t_end:
+                k = d.run_until(wl.t_end)
+            else:
+                d.step(wl.steps)
+                k = wl.steps
+            st = d.read_state()
+            d.close()
+            w = worst([rel_errors(st, ref, land)])
+            out[f"{name}_{'compensated' if comp else 'float32_state'}"] = {
+                "steps": int(k), "t_s": float(st[3]), "l2": w["l2"], "linf": w["linf"],
+                "meets_bar": bool(w["l2"] <= 1e-4 and w["linf"] <= 5e-4)}
+    return out
 
 
 def _member(k):
@@ -1015,6 +1052,10 @@ def main():
     if not a.no_float32_state:
         out["float32_state"] = bench_float32_state(a, np, torch, wl, out["value"])
         _progress(f"float32 state: {out['float32_state']['value']:.3e} cell-updates/s")
+    if not a.no_full_length:
+        out["full_length_parity"] = full_length_parity(torch)
+        _progress("full-length parity: " + ", ".join(f"{k} Linf {v['linf']:.1e}"
+                                                      for k, v in out["full_length_parity"].items()))
     if not a.no_ensemble:
         out["ensemble"] = bench_ensemble(a, torch)
         _progress(f"ensemble: {out['ensemble']['value']:.3e} cell-updates/s")

@@ -192,12 +192,12 @@ def error_vs_oracle(wl, ref, t_ref, steps, np, compensated=False):
     return out
 
 
-def measured_traffic(comp: bool, kernel: str, rows: int, tail_rpw: int = 0, tail_rows: int = 0):
+def measured_traffic(comp: bool, kernel: str, rows: int, tail_rpw: int = 0, tail_rows: int = 0, order: int = 0):
     """HBM bytes per launch of ``kernel`` (stage1 / stage2, of the float32 or
-    the compensated state) under a tiling (rows per tile, and the tail's rows
-    per tile and rows) from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    runs (scaled by the copy-kernel calibration), or None when that tiling
-    was not counted or the kernel source changed since."""
+    the compensated state) under a tiling (rows per tile, the tail's rows
+    per tile and rows, tile order) from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (scaled by the copy-kernel calibration), or None when
+    that tiling was not counted or the kernel source changed since."""
     path = TRAFFIC_FILES[comp]
     if not os.path.exists(path):
         return None
@@ -209,12 +209,12 @@ def measured_traffic(comp: bool, kernel: str, rows: int, tail_rpw: int = 0, tail
     src = hashlib.sha1(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     if vals.get("kernel_source_sha1") != src:
         return None
-    # "- stage2_rows7: one 122797917; tail1x74 120760341; ..."
-    want = f"tail{tail_rpw}x{tail_rows}" if tail_rpw else "one"
-    for item in vals.get(f"{kernel}_rows{rows}", "").split(";"):
+    # "- stage2_rows7_order1: one 122.8; 1x74 120.8; ..." (MB per launch)
+    want = f"{tail_rpw}x{tail_rows}" if tail_rpw else "one"
+    for item in vals.get(f"{kernel}_rows{rows}_order{order}", "").split(";"):
         parts = item.split()
         if len(parts) == 2 and parts[0] == want:
-            return float(parts[1])
+            return float(parts[1]) * 1e6
     return None
 
 
@@ -302,8 +302,7 @@ def roofline_of(wl, comp, r):
     til = r["tiling"][dominant - 1]
     bpl = BYTES[comp][dominant] * cells
     gbs = bpl / (ms * 1e-3) / 1e9
-    # the byte counters were taken at tile order 0
-    traffic = measured_traffic(comp, f"stage{dominant}", *til[:3]) if til[3] == 0 else None
+    traffic = measured_traffic(comp, f"stage{dominant}", *til[:4])
     vpc = valu_counted(comp, f"stage{dominant}")
     out = {
         "bound": "hbm",
@@ -338,17 +337,22 @@ def bench_single(a, np, torch):
         comp = not a.float32_state
         dom = Domain.from_workload(wl, device="cuda:0", compensated_state=comp)
         if a.count_tilings:
-            # every tiling the tuner may settle on, 3 steps each, in list order
-            # (stage k's dispatches 3i .. 3i+2 ran at its list entry i, or its last)
+            # every tiling the tuner may settle on, in each of the four tile
+            # orders, 3 steps each: order o, list entry i ran as stage k's
+            # dispatches 3 (o n + i) .. +2, with n the longer list (the
+            # shorter one repeats its last entry)
             l1, l2 = dom.list_tilings(1), dom.list_tilings(2)
-            for i in range(max(len(l1), len(l2))):
-                dom.set_stage_tiling(1, *l1[min(i, len(l1) - 1)])
-                dom.set_stage_tiling(2, *l2[min(i, len(l2) - 1)])
-                dom.step(3)
+            n = max(len(l1), len(l2))
+            for order in range(4):
+                for i in range(n):
+                    dom.set_stage_tiling(1, *l1[min(i, len(l1) - 1)], order)
+                    dom.set_stage_tiling(2, *l2[min(i, len(l2) - 1)], order)
+                    dom.step(3)
             torch.cuda.synchronize()
             _copy_calibration(a, torch)
             dom.close()
-            print(json.dumps({"counted_tilings": [l1, l2], "steps_per_tiling": 3, "compensated": comp}), flush=True)
+            print(json.dumps({"counted_tilings": [l1, l2], "orders": 4, "steps_per_tiling": 3, "compensated": comp}),
+                  flush=True)
             return None, wl
         dom.autotune()
         warm_graphs(dom, a.warmup, a.profile_steps)
@@ -411,7 +415,8 @@ def bench_float32_state(a, np, torch, wl, full_value):
     v = cells * a.steps / r["el"]
     return {"value": v, "unit": "cell-updates/s", "ms_per_step": r["el"] / a.steps * 1e3, "steps": a.steps,
             "gpu_ms_per_step": r["gpu_ms"] / a.steps, "stage1_ms": r["ms1"], "stage2_ms": r["ms2"],
-            "rows_per_wave": [t[:3] for t in r["tiling"]], "rate_vs_headline": v / full_value,
+            "rows_per_wave": [t[:3] for t in r["tiling"]], "tile_order": [t[3] for t in r["tiling"]],
+            "rate_vs_headline": v / full_value,
             "roofline": roofline_of(wl, False, r),
             "note": "same workload and timed region as the headline, compensated_state=0"}
 

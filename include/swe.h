@@ -89,8 +89,8 @@ typedef struct swe_params {
 typedef struct swe_domain swe_domain;
 
 /* Bytes of device workspace that swe_init_domain needs for these parameters
- * (state double buffer, bathymetry, Coriolis field, forcing tables, control
- * block).  max_bnd_times / max_wind_times bound the forcing snapshots that
+ * (state double buffer, bathymetry, Coriolis field -- every plane with a
+ * frame of two ghost cells on each side --, forcing tables, control block).  max_bnd_times / max_wind_times bound the forcing snapshots that
  * swe_set_forcing may later hold.  Returns SWE_E_ARG for invalid parameters. */
 int swe_workspace_bytes(const swe_params *p, int32_t max_wind_times, int32_t max_bnd_times,
                         size_t *bytes);

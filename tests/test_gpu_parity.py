@@ -201,6 +201,39 @@ def test_forcing_changes_reach_replayed_graphs():
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("comp", [False, True], ids=["f32state", "compensated"])
+def test_new_boundary_data_mid_run_matches_oracle(comp):
+    """New boundary snapshots handed over between steps reach the nested
+    ghost cells of the very next stage (the state's ghost frame is rebuilt
+    from them): 15 steps with one set of snapshots, then 15 with another
+    (0.5 m higher, momenta reversed), against the oracle restarted from its
+    state after the first 15 steps with the second set.  dt replay and own
+    dt."""
+    wl = random_small(97, 83, seed=41, steps=30, bc=(BC_NESTED,) * 4, land_frac=0.1)
+    b2 = np.array(wl.bnd, dtype=np.float32).copy()
+    b2[:, 0] += 0.5
+    b2[:, 1:] *= -1.0
+    wl2 = wl.copy(bnd=b2)
+    _say("new boundary data mid-run", "compensated" if comp else "float32 state")
+    s1, t1, dts1, k1 = O.Oracle(wl).run(nsteps=15)
+    ref, t_ref, dts2, k2 = O.Oracle(wl2).run(state=s1, t=t1, nsteps=15)
+    assert k1 == 15 and k2 == 15
+    for mode in ("replay", "own"):
+        d = _dom(wl, comp=comp)
+        if mode == "replay":
+            d.step_dt(dts1)
+        else:
+            d.step(15)
+        d.set_boundary(wl2.bnd_t, b2)
+        if mode == "replay":
+            d.step_dt(dts2)
+        else:
+            d.step(15)
+        got = d.read_state()
+        d.close()
+        assert_parity(got, ref, wl.land, label=f"new boundary data, {mode}")
+
+
 @pytest.mark.parametrize("proj", [False, True])
 def test_rossby_beta_plane_matches_oracle(proj):
     """The beta-plane Rossby-wave case of section "Coriolis force" (350 x 350

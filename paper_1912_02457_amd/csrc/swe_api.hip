@@ -402,6 +402,7 @@ int swe_init_domain(const swe_params *p, void *dev_workspace, size_t bytes, void
     D.kx = (float)(p->dx / (2.0 * p->g)); D.ky = (float)(p->dy / (2.0 * p->g));
     D.g = (float)p->g; D.theta = (float)p->theta; D.kappa = (float)p->kappa;
     D.theta2 = (float)(2.0 * p->theta);
+    D.grdx2 = (float)(0.5 * p->g / p->dx); D.grdy2 = (float)(0.5 * p->g / p->dy);
     D.inv2kappa = (float)(1.0 / (2.0 * p->kappa)); D.kappa_sq = (float)(p->kappa * p->kappa);
     D.courant_q = (float)(0.25 * p->courant);
     D.friction = p->friction;
@@ -845,7 +846,10 @@ int swe_get_stage_tiling(swe_domain *d, int32_t stage, int32_t *rows_per_wave, i
 
 // Median-based time of one stage kernel under tiling T (one warm-up and
 // eight event-timed launches, the middle two summed, so that a disturbed
-// launch does not decide).
+// launch does not decide).  Each launch follows one of the other stage
+// kernel (untimed, under its tiling `other`), as in a step: what that kernel
+// leaves in the caches, and the state it writes, are what the timed one
+// starts from.
 struct StageTimer {
     static constexpr int kReps = 8;
     hipEvent_t ev[2 * kReps] = {};
@@ -859,12 +863,17 @@ struct StageTimer {
         }
         return hipSuccess;
     }
-    hipError_t time(swe_domain *d, int stage, const Tiling &T, float *out)
+    hipError_t time(swe_domain *d, int stage, const Tiling &T, const Tiling &other, float *out)
     {
         const bool proj = d->p.north_projection != 0;
-        hipError_t he = launch_stage(stage, proj, d->dom, T, d->parity, 0.0, d->stream, nullptr, nullptr);
-        for (int k = 0; k < kReps && he == hipSuccess; ++k)
-            he = launch_stage(stage, proj, d->dom, T, d->parity, 0.0, d->stream, ev[2 * k], ev[2 * k + 1]);
+        const int ostage = 3 - stage;
+        hipError_t he = launch_stage(ostage, proj, d->dom, other, d->parity, 0.0, d->stream, nullptr, nullptr);
+        if (he == hipSuccess) he = launch_stage(stage, proj, d->dom, T, d->parity, 0.0, d->stream, nullptr, nullptr);
+        for (int k = 0; k < kReps && he == hipSuccess; ++k) {
+            he = launch_stage(ostage, proj, d->dom, other, d->parity, 0.0, d->stream, nullptr, nullptr);
+            if (he == hipSuccess)
+                he = launch_stage(stage, proj, d->dom, T, d->parity, 0.0, d->stream, ev[2 * k], ev[2 * k + 1]);
+        }
         if (he != hipSuccess || (he = hipStreamSynchronize(d->stream)) != hipSuccess) return he;
         float ms[kReps];
         for (int k = 0; k < kReps && he == hipSuccess; ++k) {
@@ -913,7 +922,7 @@ void tail_candidates(const swe_domain *d, int stage, int by, std::vector<Tiling>
 // candidates seen are timed again, twice each, and the best of those
 // measurements wins (one timing of eight launches can be off by a few per
 // cent).
-int sweep_stage(swe_domain *d, int stage, Tiling *best_T)
+int sweep_stage(swe_domain *d, int stage, const Tiling &other, Tiling *best_T)
 {
     const int nx = d->p.nx, ny = d->p.ny;
     StageTimer tm;
@@ -923,7 +932,7 @@ int sweep_stage(swe_domain *d, int stage, Tiling *best_T)
     int best_k = -1;
     std::vector<std::pair<float, Tiling>> seen;
     auto time_one = [&](const Tiling &T, float *ms) {
-        hipError_t e = tm.time(d, stage, T, ms);
+        hipError_t e = tm.time(d, stage, T, other, ms);
         if (e == hipSuccess) seen.push_back({*ms, T});
         return e;
     };
@@ -961,7 +970,7 @@ int sweep_stage(swe_domain *d, int stage, Tiling *best_T)
         for (size_t k = 0; k < seen.size() && k < 3 && he == hipSuccess; ++k)
             for (int rep = 0; rep < 2 && he == hipSuccess; ++rep) {
                 float ms = 0.f;
-                if ((he = tm.time(d, stage, seen[k].second, &ms)) != hipSuccess) break;
+                if ((he = tm.time(d, stage, seen[k].second, other, &ms)) != hipSuccess) break;
                 if (ms < conf_best) { conf_best = ms; best = seen[k].second; }
             }
     }
@@ -1043,12 +1052,10 @@ int swe_autotune_tiling(swe_domain *d, int32_t *rows_per_wave)
                                  ny, hipMemcpyDeviceToHost, d->stream));
     Tiling T1 = d->T[0], T2 = d->T[1];
     hipError_t se = settle_clocks(d);
-    rc = se != hipSuccess ? hip_fail(se, "settle_clocks") : sweep_stage(d, 1, &T1);
-    if (!rc) {
-        hipError_t e = launch_stage(1, d->p.north_projection != 0, d->dom, T1, d->parity, 0.0, d->stream, nullptr,
-                                    nullptr);
-        rc = e != hipSuccess ? hip_fail(e, "launch_stage") : sweep_stage(d, 2, &T2);
-    }
+    // stage 1 between launches of the stage-2 kernel's current tiling, then
+    // stage 2 between launches of the stage-1 tiling just found
+    rc = se != hipSuccess ? hip_fail(se, "settle_clocks") : sweep_stage(d, 1, T2, &T1);
+    if (!rc) rc = sweep_stage(d, 2, T1, &T2);
     // the state and control block go back even when the sweep failed
     for (int k = 0; k < nq; ++k)
         HIP_TRY(hipMemcpy2DAsync(q[k], d->dom.pitch * esz(k), d->pinned_state + k * plane, nx * esz(k), nx * esz(k),

@@ -88,6 +88,7 @@ struct Dom {
     float dx, dy, rdx, rdy, kx, ky; // kx = dx / (2 g)
     float g, theta, kappa, inv2kappa, kappa_sq, courant_q; // courant_q = C / 4
     float theta2;                  // 2 theta (the limiter works on twice the slopes)
+    float grdx2, grdy2;            // g / (2 dx), g / (2 dy): the bathymetry source's factors
     int friction;
     float fric_c;                  // r, r, or g n^2 (Manning)
     double inv_rho_w;

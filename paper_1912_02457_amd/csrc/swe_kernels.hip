@@ -50,6 +50,17 @@ __device__ __forceinline__ void st(float *__restrict__ base, uint32_t off, float
 }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// The same value, opaque to the compiler (an empty asm on a VGPR, no
+// instruction).  A store whose offset comes from another basic block gets
+// that offset as a 64-bit value and a 64-bit address add per plane; an
+// offset made opaque in the store's own block is widened there, so the
+// stores take the scalar-base form like the loads.
+__device__ __forceinline__ uint32_t local_off(uint32_t v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // Rounding errors of the compensated state are stored in 16 bits: the upper
 // half of the float32 error, rounded to nearest (ties away from zero), i.e. a
 // bfloat16.  An error is at most half an ulp of its value, so the pair keeps
@@ -95,25 +106,37 @@ __device__ __forceinline__ float from_left(float v) { return __int_as_float(from
 __device__ __forceinline__ float from_right(float v) { return __int_as_float(from_right(__float_as_int(v))); }
 
 // eq. desing_ours; h^2/(2 kappa) + kappa/2 is formed as (h h + kappa^2) /
-// (2 kappa), one uniform operand per instruction
+// (2 kappa), one uniform operand per instruction.  That value q is never
+// below |h| (equal only at |h| = kappa) and is below kappa exactly when |h|
+// is, so max(|h|, min(q, kappa)) is the median of |h|, q and kappa.
 __device__ __forceinline__ float desing(float h, const Dom &d)
 {
-    float lo = fminf(fmaf(h, h, d.kappa_sq) * d.inv2kappa, d.kappa);
-    float m = fmaxf(fabsf(h), lo);
+    const float q = fmaf(h, h, d.kappa_sq) * d.inv2kappa;
+    const float m = __builtin_amdgcn_fmed3f(fabsf(h), q, d.kappa);
     // sign(h) with sign(0) = +1: adding +0 turns a -0 into +0
     return copysignf(m, h + 0.f);
 }
 
 // TWICE the generalized minmod of theta*backward, central, theta*forward
-// differences: minmod(2 theta dm, dm + dp, 2 theta dp) with th2 = 2 theta
-// (scaling by two is exact, so callers take a quarter of it where the
-// slope's half is used, bitwise the same as halving the minmod).  minmod of
-// three numbers is the median of (their minimum, 0, their maximum): the
-// minimum if all are positive, the maximum if all are negative, else 0.
-__device__ __forceinline__ float limited2(float dm, float dp, float th2)
+// differences dm, dp: minmod(2 theta dm, dm + dp, 2 theta dp), given as its
+// three candidates a = 2 theta dm, b = dm + dp, c = 2 theta dp (scaling by
+// two is exact, so callers take a quarter of it where the slope's half is
+// used, bitwise the same as halving the minmod).  minmod of three numbers
+// is the median of (their minimum, 0, their maximum): the minimum if all
+// are positive, the maximum if all are negative, else 0.  Along y each
+// row's 2 theta multiple serves the faces below and above it.
+__device__ __forceinline__ float limited2(float a, float b, float c)
 {
-    const float a = th2 * dm, b = dm + dp, c = th2 * dp;
     return __builtin_amdgcn_fmed3f(fminf(a, fminf(b, c)), 0.f, fmaxf(a, fmaxf(b, c)));
+}
+
+// limited2 along x, the forward difference being the right neighbour's
+// backward one: its 2 theta multiple is the neighbour's product, moved by
+// one lane (the same bits as multiplying the moved difference)
+__device__ __forceinline__ float limited2_x(float dm, float th2)
+{
+    const float a = th2 * dm;
+    return limited2(a, dm + from_right(dm), from_right(a));
 }
 
 __device__ __forceinline__ void time_weights(int n, const double *ts, double tau, int &k, double &s)
@@ -190,12 +213,16 @@ __device__ __forceinline__ F3 cu_flux(float eL, float pL0, float qL0, float eR, 
     float den = ap - am;
     bool wet = den > 0x1p-100f;
     float w = wet ? rcp(den) : 0.f;
-    float al = wet ? ap * w : 0.5f;
-    float be = 1.f - al;
-    float ga = ap * am * w;
+    const float apw = ap * w;
+    float al = wet ? apw : 0.5f;
+    float ga = am * apw;
+    // alpha F_L + (1 - alpha) F_R as F_R + alpha (F_L - F_R): one operation
+    // less, and exactly F_R where the two physical fluxes are equal (a lake
+    // at rest)
+    const float dp = pL - pR;
     F3 r;
-    r.e = fmaf(al, pL, fmaf(be, pR, ga * (eR - eL)));
-    r.p = fmaf(al, FL, fmaf(be, FR, ga * (pR - pL)));
+    r.e = fmaf(al, dp, fmaf(ga, eR - eL, pR));
+    r.p = fmaf(al, FL - FR, fmaf(ga, -dp, FR));
     r.q = r.e * (r.e >= 0.f ? vL : vR);
     return r;
 }
@@ -219,16 +246,17 @@ __device__ __forceinline__ F3 face_flux(float eL, float pL, float qL, float eR, 
     return r;
 }
 
-// bathymetry source times dx (x) or dy (y): (g/2)(h^E + h^W)(H_E - H_W)
-// minus g (R_E^2 - R_W^2)/2, R = max(H, 0), matching the pressure flux of
+// bathymetry source times 2 dx / g (x) or 2 dy / g (y): (h^E + h^W)(H_E - H_W)
+// minus (R_E^2 - R_W^2), R = max(H, 0), matching the pressure flux of
 // cu_flux.  With h = eta + H and H^2 - max(H,0)^2 = min(H,0)^2 this is
-//   g/2 [(eta^E + eta^W)(H_E - H_W) + min(H_E,0)^2 - min(H_W,0)^2],
-// one formula for wet and dry faces with no cancellation of large terms.
-__device__ __forceinline__ float bathy_source(float eE, float eW, float HE, float HW, const Dom &d)
+//   (eta^E + eta^W)(H_E - H_W) + min(H_E,0)^2 - min(H_W,0)^2,
+// one formula for wet and dry faces with no cancellation of large terms;
+// the caller scales it by g / (2 dx) or g / (2 dy).
+__device__ __forceinline__ float bathy_source(float eE, float eW, float HE, float HW)
 {
     float mE = fminf(HE, 0.f), mW = fminf(HW, 0.f);
     float dry = fmaf(mE, mE, -(mW * mW));
-    return d.g * fmaf(0.5f * (eE + eW), HE - HW, 0.5f * dry);
+    return fmaf(eE + eW, HE - HW, dry);
 }
 
 // bed shear stress coefficient S >= 0, the source being -S (hu, hv), from the
@@ -272,18 +300,20 @@ struct Row {
     int land;
     bool anyland;          // some lane of the row is land (uniform over the wave)
     float dmL, dmU, dmV;   // y backward differences (this row minus the row below)
+    float tmL, tmU, tmV;   // the same times 2 theta
     float eN, eS, uN, vN;  // north/south face values once the row was the middle row
 };
 
 // face depths, mean depth, land flag and Coriolis terms of a row from its
-// four corner depths (south corners cs*, north corners cn*)
+// four corner depths (south corners cs*, north corners cn*); the south face
+// depth hs is the north face depth of the row below, 0.5 (cs0 + cs1)
 template <bool PROJ>
-__device__ __forceinline__ void row_terms(Row &R, float cs0, float cs1, float cn0, float cn1, float th,
+__device__ __forceinline__ void row_terms(Row &R, float cs0, float cs1, float cn0, float cn1, float hs, float th,
                                           const Dom &d)
 {
     R.Hw = 0.5f * (cs0 + cn0);
     R.He = 0.5f * (cs1 + cn1);
-    R.Hs = 0.5f * (cs0 + cs1);
+    R.Hs = hs;
     R.Hn = 0.5f * (cn0 + cn1);
     R.Hb = 0.25f * ((cs0 + cn0) + (cs1 + cn1));
     float h = R.e + R.Hb;
@@ -310,6 +340,9 @@ __device__ __forceinline__ void y_diff(Row &C, const Row &B, const Dom &d)
     C.dmL = C.e - B.e - d.ky * (B.cy + C.cy);
     C.dmU = C.u - B.u;
     C.dmV = C.v - B.v;
+    C.tmL = d.theta2 * C.dmL;
+    C.tmU = d.theta2 * C.dmU;
+    C.tmV = d.theta2 * C.dmV;
 }
 
 // limited y-slopes and N/S face values of row B (eq. hE in its N/S form with
@@ -319,10 +352,9 @@ __device__ __forceinline__ void y_faces(Row &B, const Row &C, int landA, bool an
                                         float &vS)
 {
     // twice the limited slopes (limited2)
-    const float th2 = d.theta2;
-    float sL = limited2(B.dmL, C.dmL, th2);
-    float sU = limited2(B.dmU, C.dmU, th2);
-    float sV = limited2(B.dmV, C.dmV, th2);
+    float sL = limited2(B.tmL, B.dmL + C.dmL, C.tmL);
+    float sU = limited2(B.tmU, B.dmU + C.dmU, C.tmU);
+    float sV = limited2(B.tmV, B.dmV + C.dmV, C.tmV);
     // first order next to land (skipped for rows without land nearby)
     if ((anylandA || C.anyland) && (landA || C.land)) sL = sU = sV = 0.f;
     float rho = 0.25f * sL + d.ky * B.cy;
@@ -505,10 +537,16 @@ __device__ __forceinline__ void write_frame_nested(const Dom &d, const TileCtx &
     if (d.bc[3] == BC_NESTED && y1 == ny && c.out_lane) put(2 * ny + nx + x, x, ny, x, ny + 1);
 }
 
+// lanes of a wave that stored a non-finite state, or a water depth below
+// -kappa (ballot masks, the same in every lane)
+struct BadLanes {
+    uint64_t nonfinite, negative;
+};
+
 template <int STAGE, bool PROJ, bool W10, bool COMP>
 __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 &Gn, const TileCtx &c,
                                            float e0, float u0, float v0, const FrsPre &fp,
-                                           const Dom &d, float &wmax_loc, int &bad)
+                                           const Dom &d, float &wmax_loc, BadLanes &bad)
 {
     const float th2 = d.theta2;
     float eL = from_left(A.e), cxL = from_left(A.cx);
@@ -516,9 +554,9 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
     float dmK = A.e - eL - d.kx * (cxL + A.cx);
     float dmU = A.u - uL, dmV = A.v - vL;
     // twice the limited slopes (limited2)
-    float sK = limited2(dmK, from_right(dmK), th2);
-    float sUx = limited2(dmU, from_right(dmU), th2);
-    float sVx = limited2(dmV, from_right(dmV), th2);
+    float sK = limited2_x(dmK, th2);
+    float sUx = limited2_x(dmU, th2);
+    float sVx = limited2_x(dmV, th2);
     int landR = 0;
     if (A.anyland) {  // first order next to land (rows with land only)
         const int landL = from_left(A.land);
@@ -556,10 +594,10 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
         wy += sy;
     }
     float Me = -(Fe.e - Fwe) * d.rdx - (Gn.e - Gs.e) * d.rdy;
-    float Mu = -(Fe.p - Fwp) * d.rdx - (Gn.q - Gs.q) * d.rdy + bathy_source(eE, eW, A.He, A.Hw, d) * d.rdx +
+    float Mu = -(Fe.p - Fwp) * d.rdx - (Gn.q - Gs.q) * d.rdy + bathy_source(eE, eW, A.He, A.Hw) * d.grdx2 +
                Cx + wx;
-    float Mv = -(Fe.q - Fwq) * d.rdx - (Gn.p - Gs.p) * d.rdy +
-               bathy_source(A.eN, A.eS, A.Hn, A.Hs, d) * d.rdy + Cy + wy;
+    float Mv = -(Fe.q - Fwq) * d.rdx - (Gn.p - Gs.p) * d.rdy + bathy_source(A.eN, A.eS, A.Hn, A.Hs) * d.grdy2 +
+               Cy + wy;
     const uint32_t oo = cell_off(d, c.o, c.i);
     const float dt = c.dt;
     float S = friction_coeff(d, A.ri, A.u, A.v);
@@ -643,13 +681,14 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
             }
         }
         if (store) {
-            st(d.eta, oo, en);
-            st(d.hu, oo, un);
-            st(d.hv, oo, vn);
+            const uint32_t so = local_off(oo);
+            st(d.eta, so, en);
+            st(d.hu, so, un);
+            st(d.hv, so, vn);
             if (COMP) {
-                st_lo(d.eta_lo, oo, le);
-                st_lo(d.hu_lo, oo, lu);
-                st_lo(d.hv_lo, oo, lv);
+                st_lo(d.eta_lo, so, le);
+                st_lo(d.hu_lo, so, lu);
+                st_lo(d.hv_lo, so, lv);
             }
             if (c.edge) write_frame_copies<2>(d, c, en, un, vn);
         }
@@ -661,9 +700,12 @@ __device__ __forceinline__ void finish_row(const Row &A, const F3 &Gs, const F3 
         float w = fmaxf((fabsf(un * ri) + cw) * d.rdx, (fabsf(vn * ri) + cw) * d.rdy);
         wmax_loc = store ? fmaxf(wmax_loc, w) : wmax_loc;
         // bit 0: a non-finite state; bit 1: a water depth below -kappa (the
-        // scheme keeps h >= 0 under its CFL bound, so this means breakdown)
-        const int nonfin = (isfinite(en) && isfinite(un) && isfinite(vn)) ? 0 : 1;
-        bad |= store ? (nonfin | (h < -d.kappa ? 2 : 0)) : 0;
+        // scheme keeps h >= 0 under its CFL bound, so this means breakdown);
+        // gathered over the wave by ballot, so the bits are scalar values
+        const uint64_t m_st = __builtin_amdgcn_ballot_w64(store);
+        bad.nonfinite |= m_st & (__builtin_amdgcn_ballot_w64(!isfinite(en)) | __builtin_amdgcn_ballot_w64(!isfinite(un)) |
+                                 __builtin_amdgcn_ballot_w64(!isfinite(vn)));
+        bad.negative |= m_st & __builtin_amdgcn_ballot_w64(h < -d.kappa);
     }
 }
 
@@ -698,7 +740,7 @@ __device__ __forceinline__ RawRow load_row(const Dom &d, const float *__restrict
 
 template <int STAGE, bool PROJ, bool W10, bool COMP>
 __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1, bool frs, bool edge, float &wmax_loc,
-                                         int &bad)
+                                         BadLanes &bad)
 {
     const float *__restrict__ E = STAGE == 1 ? d.eta : d.eta1;
     const float *__restrict__ U = STAGE == 1 ? d.hu : d.hu1;
@@ -713,27 +755,29 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
     const int klast = y1 + 1;
     RawRow nxt = load_row<PROJ>(d, E, U, V, il, y0 - 2);
 
-    auto load = [&](Row &C, int k) {
+    // B: the row below C, whose north face depth is C's south one
+    auto load = [&](Row &C, const Row &B, int k) {
         RawRow cur = nxt;
         // unconditional (the last row reloads itself), so that the memory
         // counter is the same on every path and a wait for this row's own
         // loads never has to drain the prefetch of the next one
         nxt = load_row<PROJ>(d, E, U, V, il, min(k + 1, klast));
         C.e = cur.e; C.u = cur.u; C.v = cur.v; C.f = cur.f;
-        row_terms<PROJ>(C, cs0, cs1, cur.cn0, cur.cn1, cur.th, d);
+        row_terms<PROJ>(C, cs0, cs1, cur.cn0, cur.cn1, B.Hn, cur.th, d);
         cs0 = cur.cn0;
         cs1 = cur.cn1;
     };
 
     Row R0, R1, R2;
     float uS, vS;
-    load(R0, y0 - 2);
-    load(R1, y0 - 1);
+    R2.Hn = 0.5f * (cs0 + cs1);  // the face below the first row
+    load(R0, R2, y0 - 2);
+    load(R1, R0, y0 - 1);
     y_diff(R1, R0, d);
-    load(R2, y0);
+    load(R2, R1, y0);
     y_diff(R2, R1, d);
     y_faces(R1, R2, R0.land, R0.anyland, d, uS, vS);
-    load(R0, y0 + 1);
+    load(R0, R2, y0 + 1);
     y_diff(R0, R2, d);
     y_faces(R2, R0, R1.land, R1.anyland, d, uS, vS);
     F3 Gs = y_flux(R1, R2, uS, vS, d);
@@ -755,7 +799,7 @@ __device__ __forceinline__ void run_tile(const Dom &d, TileCtx c, int y0, int y1
             frs_side(d, c.i, c.o, best, dd);
             fp.zone = c.out_lane && best >= 0 && dd < d.frs_w;
         }
-        load(C, k);
+        load(C, B, k);
         y_diff(C, B, d);
         float us, vs;
         y_faces(B, C, A.land, A.anyland, d, us, vs);
@@ -895,7 +939,7 @@ __device__ __forceinline__ void process_tile(const Dom &d, const Tiling &T, int 
     frame_copy_cols(d, c.i, c.fca, c.fcb);
     if (edge && d.nb > 0) time_weights(d.nb, d.bnd_t, STAGE == 1 ? st.tn + st.dtd : st.tnext, c.fbk, c.fbs);
     float wmax_loc = 0.f;
-    int bad = 0;
+    BadLanes bad{0, 0};
     // one row loop for every tile (a second variant of it in the same kernel
     // raised the register count of both by ~25 VGPRs): the relaxation zone
     // and the frame writes are uniform branches
@@ -903,7 +947,7 @@ __device__ __forceinline__ void process_tile(const Dom &d, const Tiling &T, int 
 
     if (STAGE == 2) {
         wmax_loc = wave_max(wmax_loc);
-        const uint32_t fl = (__ballot(bad & 1) ? 1u : 0u) | (__ballot(bad & 2) ? 2u : 0u);
+        const uint32_t fl = (bad.nonfinite ? 1u : 0u) | (bad.negative ? 2u : 0u);
         if (lane == 0) {
             atomicMax(&d.ctrl->wslot[parity ^ 1][tile & (kCflSlots - 1)][0], __float_as_uint(wmax_loc));
             if (fl) atomicOr(&d.ctrl->flags, fl);

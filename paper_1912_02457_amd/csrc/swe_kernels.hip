@@ -108,9 +108,7 @@ __device__ __forceinline__ float from_right(float v) { return __int_as_float(fro
 // eq. desing_ours; h^2/(2 kappa) + kappa/2 is formed as (h h + kappa^2) /
 // (2 kappa), one uniform operand per instruction.  That value q is never
 // below |h| (equal only at |h| = kappa) and is below kappa exactly when |h|
-// is, so max(|h|, min(q, kappa)) is the median of |h|, q and kappa (just
-// above |h| = kappa the rounded q can fall an ulp below |h|; the median then
-// takes q, the same formula to within that ulp).
+// is, so max(|h|, min(q, kappa)) is the median of |h|, q and kappa.
 __device__ __forceinline__ float desing(float h, const Dom &d)
 {
     const float q = fmaf(h, h, d.kappa_sq) * d.inv2kappa;

@@ -389,7 +389,7 @@ def bench_single(a, np, torch):
             "nx": wl.nx, "ny": wl.ny, "dx_m": wl.dx, "cells": cells, "land_fraction": land_cells / cells,
             "boundaries": "nested (M2 tide, hourly snapshots) on all sides", "friction": "linear r=3e-3 m/s",
             "wind_stress_Nm2": 0.1, "courant": wl.courant, "dt_s": r["dt_next"],
-            "state": "compensated (float32 value + float32 rounding error per field); float32 arithmetic",
+            "state": "compensated (float32 value + its rounding error kept to 16 bits, per field); float32 arithmetic",
             "rows_per_wave": [rw1, rw2], "tail_rows_per_wave": [trw1, trw2], "tail_rows": [tr1, tr2],
             "tile_order": [ord1, ord2], "waves_per_stage": [wv1, wv2],
             "tiling": "measured per stage kernel before the timed region (swe_autotune_tiling)",

@@ -81,6 +81,11 @@ CASES = [
     ("tall", 7, 301, dict(bc=(BC_PERIODIC, BC_PERIODIC, BC_NESTED, BC_NESTED), friction=FRIC_LINEAR,
                           friction_coeff=1e-3)),
     ("anisotropic", 150, 40, dict(dx=300.0, dy=900.0, land_frac=0.15, wind=(0.2, -0.1))),
+    # mostly land: a few lakes and channels, many rows and tiles without water
+    ("mostly_land", 90, 70, dict(land_frac=0.85, bc=(BC_NESTED, BC_WALL, BC_WALL, BC_NESTED), wind=(0.1, -0.05))),
+    # a dry shoal and a land mask together (wet-dry fix next to land faces)
+    ("wet_dry_land", 110, 80, dict(wet_dry=True, land_frac=0.3, friction=FRIC_QUADRATIC, friction_coeff=2e-3,
+                                   amp=0.5)),
 ]
 
 
